@@ -1,0 +1,23 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package only *generates inputs*: the Q1 hexahedral elasticity problem (mesh,
+coordinates, clamped face, per-element materials, element stiffness blocks as a
+blocked COO stream, right-hand sides) and random blocked-sparse fixtures.  It holds
+none of the solver's arithmetic (no SpMV, no Galerkin product, no aggregation, no
+smoother, no Krylov method), so the CPU oracle and the GPU path can both consume it
+without sharing any of the method.
+"""
+from .q1 import (  # noqa: F401
+    Q1Mesh,
+    make_mesh,
+    reference_element_matrices,
+    element_matrix,
+    materials,
+    homogeneous_materials,
+    lame,
+    coo_indices,
+    coo_values,
+    rhs,
+    stream_sizes,
+)
+from .random_bsr import random_bsr, random_spd_bsr, random_coo_stream  # noqa: F401
