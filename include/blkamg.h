@@ -1,0 +1,244 @@
+/*
+ * blkamg.h - C ABI of the natively blocked smoothed-aggregation AMG solve phase
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the recurring ("hot") work of a blocked SA-AMG solve for
+ * vector PDEs (paper §3.1): the numeric Galerkin recompute A_c = P^T A P on fixed
+ * block patterns, the V-cycle inside preconditioned CG, rectangular-block SpMV and
+ * SpMV-transpose, and blocked COO value assembly.  Blocks are dense bs_r x bs_c and
+ * may be rectangular (3x3 fine operator, 3x6 prolongator, 6x6 coarse operators;
+ * paper §2.3).  A one-time host setup (aggregation, tentative prolongator) is
+ * included so that the hierarchy can be built without any other software.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: 0 (BLKAMG_OK) on success, BLKAMG_ENOCONV (1) when an iteration
+ *   limit is reached (results are still written), a negative code on failure.
+ *   blkamg_last_error() returns a thread-local message describing the last failure.
+ *   No C++ exception crosses the ABI.
+ * - Pointers named d_* are device pointers (HIP device memory of the current
+ *   device); h_* are host pointers.  Indices are int32.  Block values are stored
+ *   block after block, each block row-major (bs_r rows of bs_c values).
+ * - Vectors are row-major [n][nrhs]: the nrhs right-hand sides of one scalar dof
+ *   are contiguous.  A block vector of a matrix with nb block rows of size bs has
+ *   n = nb * bs entries per right-hand side.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls marked "async" only enqueue work on that stream; calls marked "sync"
+ *   wait for the stream before returning.  Asynchronous kernel faults surface at
+ *   the next synchronising call.
+ * - Borrowed device arrays must stay valid, and their pattern (rowptr/colidx)
+ *   unchanged, for the lifetime of every handle that refers to them.
+ * - The library allocates its own device memory (plans, caches, library-owned
+ *   matrices, hierarchy work vectors) with hipMalloc at create/setup time; the
+ *   hot calls (spmv, ptap_numeric, coo_assemble_blocked, vcycle_apply, pcg_solve
+ *   after its first call on a hierarchy) allocate nothing.
+ */
+#ifndef BLKAMG_H
+#define BLKAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define BLKAMG_OK 0
+#define BLKAMG_ENOCONV 1     /* maximum iterations reached, not converged */
+#define BLKAMG_EINVAL (-1)   /* invalid argument, shape or state */
+#define BLKAMG_ENOMEM (-2)   /* device or host allocation failed */
+#define BLKAMG_EHIP (-3)     /* a HIP runtime call failed */
+#define BLKAMG_ESTATE (-4)   /* handle used out of order / pattern changed */
+#define BLKAMG_EBREAKDOWN (-5) /* CG breakdown: p^T A p <= 0 (matrix or M not SPD) */
+#define BLKAMG_ENOTSPD (-6)  /* coarsest Cholesky found a non-positive pivot */
+
+/* ---- value types --------------------------------------------------------- */
+#define BLKAMG_F64 0
+#define BLKAMG_F32 1
+#define BLKAMG_BF16 2        /* bfloat16 (round to nearest even); matrix values only */
+
+/* COO assembly modes */
+#define BLKAMG_INSERT 0
+#define BLKAMG_ADD 1
+
+typedef struct bsr_s* bsr_t;
+typedef struct coo_plan_s* coo_plan_t;
+typedef struct amg_s* amg_t;
+
+/* Thread-local text of the last error ("" if none).  Never NULL. */
+const char* blkamg_last_error(void);
+/* Library version as an integer (major*10000 + minor*100 + patch). */
+int blkamg_version(void);
+
+/* ==========================================================================
+ * Rectangular-block sparse matrix (paper §2.3, §2.4: independent row and column
+ * block sizes; one int32 column index per block).
+ * ========================================================================== */
+
+/* Wrap caller-owned device arrays as a block matrix.
+ *   nbr, nbc     : block rows / block columns (>= 0)
+ *   bs_r, bs_c   : block shape, each in 1..8
+ *   nnzb         : stored blocks; d_rowptr[nbr] must equal nnzb
+ *   d_rowptr     : int32[nbr+1], d_colidx: int32[nnzb] (ascending within a row)
+ *   d_val        : nnzb * bs_r * bs_c values of type `dtype`
+ * Borrowed: the handle stores the pointers only.  Validation of the pattern
+ * (monotone rowptr, column range, sorted rows) is done when the environment
+ * variable BLKAMG_VALIDATE=1 is set (sync, copies the pattern to the host).
+ * Errors: EINVAL for bad sizes/pointers.  Host-only; no device work otherwise. */
+int bsr_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t nnzb,
+               const int32_t* d_rowptr, const int32_t* d_colidx, void* d_val,
+               int dtype, bsr_t* out);
+/* Free the handle and everything it owns (caches; for library-created matrices
+ * also the arrays).  NULL is accepted. */
+int bsr_destroy(bsr_t A);
+/* Declare that the values changed: bumps the value-state stamp that gates the
+ * cached transpose and the prolongator-side data of the Galerkin product
+ * (the object-state gating of paper §3.5). */
+int bsr_mark_modified(bsr_t A);
+/* Shape, size, value type and current value-state stamp. */
+int bsr_info(bsr_t A, int32_t* nbr, int32_t* nbc, int32_t* bs_r, int32_t* bs_c,
+             int64_t* nnzb, int* dtype, uint64_t* stamp);
+/* Device arrays of the matrix (borrowed or library-owned). */
+int bsr_arrays(bsr_t A, const int32_t** d_rowptr, const int32_t** d_colidx, void** d_val);
+
+/* y = alpha * A x + beta * y   (the blocked MatMult of paper §4.2).
+ *   x: [nbc*bs_c][nrhs], y: [nbr*bs_r][nrhs], both of `vec_dtype`
+ *   (F64 with F64 matrices; F32 with F32 or BF16 matrices), nrhs in 1..8.
+ * beta == 0 overwrites y (NaNs in y are not propagated).  Async. */
+int bsr_spmv(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
+             int vec_dtype, int32_t nrhs, void* stream);
+/* y = alpha * A^T x + beta * y through a cached explicit transpose R = A^T
+ * (the cached restriction of paper §3.5).  x: [nbr*bs_r][nrhs],
+ * y: [nbc*bs_c][nrhs].  The transpose pattern is built on the first call (sync,
+ * allocates); its values are refreshed on the stream whenever the value stamp
+ * changed since they were last copied.  Async afterwards. */
+int bsr_spmv_t(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
+               int vec_dtype, int32_t nrhs, void* stream);
+
+/* ==========================================================================
+ * Galerkin coarse operator A_c = P^T A P (paper §2.1, §3.1, §3.5)
+ * ========================================================================== */
+
+/* Symbolic phase: builds the structural pattern of A_c (no numerical dropping)
+ * and the numeric plan (pattern of A P, explicit transpose of P), records P's
+ * value stamp, and creates C (library-owned, nbr = nbc = P.nbc, block
+ * P.bs_c x P.bs_c, value type of A).  Requirements: A square-blocked
+ * (bs_r == bs_c == P.bs_r), A.nbr == A.nbc == P.nbr; A F64 with P F64, or A F32
+ * with P F32 or BF16.  Sync (host pattern work).  *C must be destroyed with
+ * bsr_destroy. */
+int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream);
+/* Numeric phase: C.values = P^T A P on the fixed pattern.  If P's value stamp
+ * differs from the one cached, the prolongator-side cache (transpose values) is
+ * refreshed first on the stream; if P's or A's block count changed, returns
+ * ESTATE.  C must come from ptap_symbolic(A, P).  No allocation, no host
+ * synchronisation.  Async. */
+int ptap_numeric(bsr_t A, bsr_t P, bsr_t C, void* stream);
+
+/* ==========================================================================
+ * Blocked COO assembly (paper §3.4 and §5)
+ * ========================================================================== */
+
+/* Preallocation: from n block coordinates (h_i[k], h_j[k]) (host arrays; a
+ * negative i or j marks an entry that is ignored) build the sorted unique block
+ * pattern and the duplicate-summation plan, and create the matrix *A_out
+ * (library-owned, values zero, type `val_dtype`).  Coordinates >= nbr / nbc are
+ * EINVAL.  The index map is the stable order of the valid entries by
+ * (row, column, position).  Sync.  Free with coo_plan_destroy and bsr_destroy. */
+int coo_plan_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t n,
+                    const int32_t* h_i, const int32_t* h_j, int val_dtype,
+                    coo_plan_t* plan, bsr_t* A_out);
+int coo_plan_destroy(coo_plan_t plan);
+/* The plan's index map: d_perm int32[n_valid] (positions of valid entries in
+ * sorted order) and d_seg int32[nnzb+1] (block t sums perm[seg[t]..seg[t+1])).
+ * Device pointers owned by the plan. */
+int coo_plan_map(coo_plan_t plan, const int32_t** d_perm, const int32_t** d_seg,
+                 int64_t* n_valid, int64_t* nnzb);
+/* Numeric assembly: for each stored block t of A,
+ *   INSERT: A_t  = sum_{k in run(t)} V_k        ADD: A_t += sum V_k
+ * summed in stream order (deterministic, no atomics).  d_vals holds n blocks of
+ * bs_r*bs_c values (same order as the coordinates) of type val_dtype == A's type.
+ * A must be the matrix created with the plan (or have its exact pattern).  Async. */
+int coo_assemble_blocked(coo_plan_t plan, const void* d_vals, int val_dtype, int mode,
+                         bsr_t A, void* stream);
+
+/* ==========================================================================
+ * Smoothed-aggregation hierarchy and solve (paper §2.1, §2.2, §3.1, §4.1)
+ * ========================================================================== */
+
+typedef struct {
+  int32_t max_levels;       /* maximum number of levels (>= 1), default 10 */
+  int32_t coarse_eq_limit;  /* stop coarsening at <= this many dofs, default 1000 */
+  double strength_eps;      /* strength threshold epsilon (paper §2.2), default 0 */
+  int32_t cheb_degree;      /* Chebyshev polynomial degree (>= 1), default 2 */
+  double cheb_lo, cheb_hi;  /* Chebyshev interval as fractions of lambda_hat, 0.1 / 1.1 */
+  int32_t lanczos_steps;    /* Lanczos steps for lambda_hat (2..64), default 10 */
+  uint64_t lanczos_seed;    /* start-vector seed, level l uses seed + l, default 0x5EED */
+  double omega_scale;       /* prolongator-smoothing weight omega = omega_scale / lambda_hat, 4/3 */
+  int32_t hier_dtype;       /* F64 or F32: type of the level operators, smoother and V-cycle */
+  int32_t p_dtype;          /* type of the stored prolongators: F64 (with F64), F32 or BF16 (with F32) */
+} blkamg_opts;
+
+/* Fill *o with the defaults listed above. */
+void blkamg_opts_default(blkamg_opts* o);
+
+/* Host-only greedy aggregation (paper §2.2 "greedy disjoint covering", paper §3.2
+ * graph over blocks), the structural case epsilon = 0: vertices are the block rows
+ * with h_dirichlet[i] == 0; neighbours are the other stored columns of the row
+ * that are not Dirichlet.  Phase 1 visits rows in natural order and makes a row
+ * whose neighbours are all unaggregated the root of {row} + neighbours; phase 2
+ * puts each leftover row into the phase-1 aggregate holding most of its
+ * neighbours (ties: smallest id).  h_agg[i] = aggregate id or -1 (Dirichlet).
+ * h_rowptr/h_colidx: host pattern.  h_dirichlet may be NULL.  Pure host code. */
+int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
+                 const uint8_t* h_dirichlet, int32_t* h_agg, int32_t* n_agg);
+
+/* Build the hierarchy from the fine operator A0 (square blocks bs = A0.bs_r, F64):
+ * per level aggregate, tentative prolongator from the near-null space (thin QR per
+ * aggregate, positive diagonal of R), lambda_hat by Lanczos, P = (I - omega D^-1 A) P~
+ * with D the block diagonal, A_c = P^T A P; coarsest level factored by dense
+ * Cholesky.  h_coords: [nbr][3] node coordinates (bs must be 3: the six rigid-body
+ * modes are generated) ; h_dirichlet: [nbr] flags (may be NULL).  A0 is borrowed
+ * and must outlive the hierarchy.  Sync; allocates. */
+int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet,
+              const blkamg_opts* opts, void* stream, amg_t* out);
+int amg_destroy(amg_t M);
+int amg_num_levels(amg_t M, int32_t* n_levels);
+/* Level operators (library-owned; level 0 is A0 itself for F64 hierarchies and a
+ * library-owned F32 copy for F32 hierarchies) and prolongators (NULL on the
+ * coarsest level).  Handles remain owned by the hierarchy. */
+int amg_level(amg_t M, int32_t level, bsr_t* A, bsr_t* P);
+/* Host copy of the aggregates of `level` (int32[nbr of that level]). */
+int amg_aggregates(amg_t M, int32_t level, int32_t* h_agg);
+/* Host copy of lambda_hat per level (double[n_levels-1]).  Sync. */
+int amg_lambdas(amg_t M, double* h_lam);
+/* Hot Galerkin recompute with reused interpolation (paper §3.1, §3.5): after A0's
+ * values changed, recompute every coarse operator with ptap_numeric on the fixed
+ * patterns (F32 hierarchies first cast A0 to their F32 copy).  Async, no allocation. */
+int amg_galerkin_recompute(amg_t M, void* stream);
+/* Refresh the smoother data after a recompute: block-diagonal inverses,
+ * lambda_hat (Lanczos, or taken from h_lambda[level] when h_lambda != NULL),
+ * Chebyshev coefficients and the coarsest Cholesky factor.  Returns ENOTSPD if the
+ * factorisation meets a non-positive pivot (sync check at the end).  Sync. */
+int amg_smoother_refresh(amg_t M, const double* h_lambda, void* stream);
+
+/* One V-cycle from a zero guess, z = M^-1 r (paper §2.1): Chebyshev/point-block-
+ * Jacobi pre-smoothing, residual, restriction with P^T, recursion, prolongation,
+ * post-smoothing, coarsest solve with the Cholesky factor.  d_r, d_z: F64
+ * [n_dof(A0)][nrhs], nrhs in 1..8 (F32 hierarchies convert at entry and exit).
+ * Async. */
+int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* stream);
+
+/* Preconditioned CG on A x = b (the CG accelerator of paper §4.1) from x0 = 0 with
+ * M = one V-cycle; stops when the recurrence residual satisfies
+ * ||r||_2 <= rtol ||b||_2 (unpreconditioned norm, paper §4.1) or after maxit
+ * iterations.  A: F64, n_dof = A0's; d_b, d_x: F64 [n_dof] (nrhs must be 1).
+ * *iters = number of solution updates; *relres = ||r||/||b||.  Returns ENOCONV at
+ * maxit, EBREAKDOWN if p^T A p <= 0.  Sync (one 8-byte read per iteration). */
+int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol,
+              int32_t maxit, int32_t nrhs, int32_t* iters, double* relres, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLKAMG_H */

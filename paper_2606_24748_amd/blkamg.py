@@ -1,0 +1,346 @@
+"""ctypes binding of libblkamg (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (include/blkamg.h)
+and passes device pointers taken from torch tensors plus the current HIP stream.
+No computation happens in Python: if the shared library is missing, importing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblkamg.so")
+
+OK, ENOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EBREAKDOWN, ENOTSPD = 0, 1, -1, -2, -3, -4, -5, -6
+F64, F32, BF16 = 0, 1, 2
+INSERT, ADD = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2606_24748_amd/build.py (or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+_p = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_u64 = C.c_uint64
+_f64 = C.c_double
+_pi32 = C.POINTER(C.c_int32)
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("max_levels", C.c_int32),
+        ("coarse_eq_limit", C.c_int32),
+        ("strength_eps", C.c_double),
+        ("cheb_degree", C.c_int32),
+        ("cheb_lo", C.c_double),
+        ("cheb_hi", C.c_double),
+        ("lanczos_steps", C.c_int32),
+        ("lanczos_seed", C.c_uint64),
+        ("omega_scale", C.c_double),
+        ("hier_dtype", C.c_int32),
+        ("p_dtype", C.c_int32),
+    ]
+
+
+_SIG = {
+    "blkamg_last_error": (C.c_char_p, []),
+    "blkamg_version": (C.c_int, []),
+    "bsr_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, _p, C.c_int, C.POINTER(_p)]),
+    "bsr_destroy": (C.c_int, [_p]),
+    "bsr_mark_modified": (C.c_int, [_p]),
+    "bsr_info": (C.c_int, [_p, _pi32, _pi32, _pi32, _pi32, C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(_u64)]),
+    "bsr_arrays": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p)]),
+    "bsr_spmv": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
+    "bsr_spmv_t": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
+    "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
+    "ptap_numeric": (C.c_int, [_p, _p, _p, _p]),
+    "coo_plan_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, C.c_int, C.POINTER(_p), C.POINTER(_p)]),
+    "coo_plan_destroy": (C.c_int, [_p]),
+    "coo_plan_map": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_i64), C.POINTER(_i64)]),
+    "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
+    "blkamg_opts_default": (None, [C.POINTER(Opts)]),
+    "sa_aggregate": (C.c_int, [_i32, _p, _p, _p, _p, _pi32]),
+    "amg_setup": (C.c_int, [_p, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
+    "amg_destroy": (C.c_int, [_p]),
+    "amg_num_levels": (C.c_int, [_p, _pi32]),
+    "amg_level": (C.c_int, [_p, _i32, C.POINTER(_p), C.POINTER(_p)]),
+    "amg_aggregates": (C.c_int, [_p, _i32, _p]),
+    "amg_lambdas": (C.c_int, [_p, _p]),
+    "amg_galerkin_recompute": (C.c_int, [_p, _p]),
+    "amg_smoother_refresh": (C.c_int, [_p, _p, _p]),
+    "vcycle_apply": (C.c_int, [_p, _p, _p, _i32, _p]),
+    "pcg_solve": (C.c_int, [_p, _p, _p, _p, _f64, _i32, _i32, _pi32, C.POINTER(_f64), _p]),
+}
+
+for _name, (_res, _args) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class BlkAmgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.blkamg_last_error().decode()
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str, allow=(OK,)) -> int:
+    if code not in allow:
+        raise BlkAmgError(code, where)
+    return code
+
+
+def exported_symbols():
+    return list(_SIG)
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+_DT = {"float64": F64, "float32": F32, "bfloat16": BF16}
+
+
+def dtype_code(t) -> int:
+    return _DT[str(t.dtype).replace("torch.", "")]
+
+
+def _torch_dtype(code):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[code]
+
+
+# ------------------------------------------------------------------------------
+# handles
+# ------------------------------------------------------------------------------
+class Bsr:
+    """Block sparse matrix handle.  Keeps the tensors it borrows alive."""
+
+    def __init__(self, handle, keep=(), owned_by_lib=True, owner=None):
+        self.h = C.c_void_p(handle) if not isinstance(handle, C.c_void_p) else handle
+        self._keep = keep
+        self._destroy = owned_by_lib and owner is None
+        self._owner = owner
+
+    def __del__(self):
+        if getattr(self, "_destroy", False) and self.h:
+            _lib.bsr_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        nbr, nbc, br, bc = _i32(), _i32(), _i32(), _i32()
+        nnzb, dt, st = _i64(), C.c_int(), _u64()
+        _check(_lib.bsr_info(self.h, nbr, nbc, br, bc, nnzb, dt, st), "bsr_info")
+        return dict(nbr=nbr.value, nbc=nbc.value, bs_r=br.value, bs_c=bc.value, nnzb=nnzb.value,
+                    dtype=dt.value, stamp=st.value)
+
+    def arrays(self):
+        """Copies of the device arrays as torch tensors (rowptr, colidx, values[nnzb, bs_r, bs_c])."""
+        import torch
+        inf = self.info()
+        rp, ci, v = _p(), _p(), _p()
+        _check(_lib.bsr_arrays(self.h, rp, ci, v), "bsr_arrays")
+        nvals = inf["nnzb"] * inf["bs_r"] * inf["bs_c"]
+        vals = _from_ptr(v.value, nvals, _torch_dtype(inf["dtype"]))
+        return (_from_ptr(rp.value, inf["nbr"] + 1, torch.int32), _from_ptr(ci.value, inf["nnzb"], torch.int32),
+                vals.view(inf["nnzb"], inf["bs_r"], inf["bs_c"]))
+
+
+def _from_ptr(ptr, n, dtype):
+    """Device-to-device copy of library-owned memory into a new torch tensor."""
+    import torch
+    out = torch.empty(n, dtype=dtype, device="cuda")
+    if n == 0 or not ptr:
+        return out
+    torch.cuda.synchronize()
+    rc = _hip().hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), C.c_size_t(n * out.element_size()), 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out
+
+
+_HIP = None
+
+
+def _hip():
+    global _HIP
+    if _HIP is None:
+        _HIP = C.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.restype = C.c_int
+        _HIP.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _HIP
+
+
+def bsr_create(nbr, nbc, bs_r, bs_c, rowptr, colidx, val) -> Bsr:
+    """Wrap torch device tensors (int32 rowptr/colidx, float64/float32/bfloat16 values)."""
+    h = _p()
+    nnzb = int(colidx.numel())
+    _check(_lib.bsr_create(nbr, nbc, bs_r, bs_c, nnzb, _ptr(rowptr), _ptr(colidx), _ptr(val),
+                           dtype_code(val), C.byref(h)), "bsr_create")
+    return Bsr(h, keep=(rowptr, colidx, val))
+
+
+def bsr_mark_modified(A: Bsr):
+    _check(_lib.bsr_mark_modified(A.h), "bsr_mark_modified")
+
+
+def bsr_spmv(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
+    _check(_lib.bsr_spmv(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs, _stream(stream)),
+           "bsr_spmv")
+
+
+def bsr_spmv_t(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
+    _check(_lib.bsr_spmv_t(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs, _stream(stream)),
+           "bsr_spmv_t")
+
+
+def ptap_symbolic(A: Bsr, P: Bsr, stream=None) -> Bsr:
+    h = _p()
+    _check(_lib.ptap_symbolic(A.h, P.h, C.byref(h), _stream(stream)), "ptap_symbolic")
+    return Bsr(h, keep=(A, P))
+
+
+def ptap_numeric(A: Bsr, P: Bsr, Cm: Bsr, stream=None):
+    _check(_lib.ptap_numeric(A.h, P.h, Cm.h, _stream(stream)), "ptap_numeric")
+
+
+class CooPlan:
+    def __init__(self, h):
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.coo_plan_destroy(self.h)
+            self.h = None
+
+    def index_map(self):
+        import torch
+        perm, seg, nv, nb = _p(), _p(), _i64(), _i64()
+        _check(_lib.coo_plan_map(self.h, perm, seg, nv, nb), "coo_plan_map")
+        return _from_ptr(perm.value, nv.value, torch.int32), _from_ptr(seg.value, nb.value + 1, torch.int32)
+
+
+def coo_plan_create(nbr, nbc, bs_r, bs_c, i: np.ndarray, j: np.ndarray, val_dtype=F64):
+    """Host coordinate arrays (int32 numpy); returns (plan, A) with A library-owned."""
+    i = np.ascontiguousarray(i, dtype=np.int32)
+    j = np.ascontiguousarray(j, dtype=np.int32)
+    plan, A = _p(), _p()
+    _check(_lib.coo_plan_create(nbr, nbc, bs_r, bs_c, len(i), i.ctypes.data_as(_p), j.ctypes.data_as(_p),
+                                val_dtype, C.byref(plan), C.byref(A)), "coo_plan_create")
+    return CooPlan(plan), Bsr(A)
+
+
+def coo_assemble_blocked(plan: CooPlan, vals, mode, A: Bsr, stream=None):
+    _check(_lib.coo_assemble_blocked(plan.h, _ptr(vals), dtype_code(vals), mode, A.h, _stream(stream)),
+           "coo_assemble_blocked")
+
+
+def blkamg_opts_default() -> Opts:
+    o = Opts()
+    _lib.blkamg_opts_default(C.byref(o))
+    return o
+
+
+def sa_aggregate(rowptr: np.ndarray, colidx: np.ndarray, dirichlet=None):
+    """Host-only greedy aggregation; returns (agg int32[nbr], n_agg)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    nbr = len(rowptr) - 1
+    agg = np.empty(nbr, dtype=np.int32)
+    n = _i32()
+    d = None
+    if dirichlet is not None:
+        dd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        d = dd.ctypes.data_as(_p)
+    _check(_lib.sa_aggregate(nbr, rowptr.ctypes.data_as(_p), colidx.ctypes.data_as(_p), d,
+                             agg.ctypes.data_as(_p), C.byref(n)), "sa_aggregate")
+    return agg, n.value
+
+
+class Amg:
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.amg_destroy(self.h)
+            self.h = None
+
+    def num_levels(self) -> int:
+        n = _i32()
+        _check(_lib.amg_num_levels(self.h, C.byref(n)), "amg_num_levels")
+        return n.value
+
+    def level(self, l):
+        A, P = _p(), _p()
+        _check(_lib.amg_level(self.h, l, C.byref(A), C.byref(P)), "amg_level")
+        return (Bsr(A, owner=self), Bsr(P, owner=self) if P.value else None)
+
+    def aggregates(self, l):
+        A, _ = self.level(l)
+        agg = np.empty(A.info()["nbr"], dtype=np.int32)
+        _check(_lib.amg_aggregates(self.h, l, agg.ctypes.data_as(_p)), "amg_aggregates")
+        return agg
+
+    def lambdas(self):
+        lam = np.zeros(max(self.num_levels() - 1, 0))
+        if len(lam):
+            _check(_lib.amg_lambdas(self.h, lam.ctypes.data_as(_p)), "amg_lambdas")
+        return lam
+
+
+def amg_setup(A0: Bsr, coords: np.ndarray, dirichlet=None, opts: Opts | None = None, stream=None) -> Amg:
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    d = None
+    dd = None
+    if dirichlet is not None:
+        dd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        d = dd.ctypes.data_as(_p)
+    o = opts or blkamg_opts_default()
+    h = _p()
+    _check(_lib.amg_setup(A0.h, coords.ctypes.data_as(_p), d, C.byref(o), _stream(stream), C.byref(h)),
+           "amg_setup")
+    return Amg(h, keep=(A0,))
+
+
+def amg_galerkin_recompute(M: Amg, stream=None):
+    _check(_lib.amg_galerkin_recompute(M.h, _stream(stream)), "amg_galerkin_recompute")
+
+
+def amg_smoother_refresh(M: Amg, lambdas=None, stream=None):
+    lam = None
+    if lambdas is not None:
+        lam_arr = np.ascontiguousarray(lambdas, dtype=np.float64)
+        lam = lam_arr.ctypes.data_as(_p)
+    _check(_lib.amg_smoother_refresh(M.h, lam, _stream(stream)), "amg_smoother_refresh")
+
+
+def vcycle_apply(M: Amg, r, z, nrhs=1, stream=None):
+    _check(_lib.vcycle_apply(M.h, _ptr(r), _ptr(z), nrhs, _stream(stream)), "vcycle_apply")
+
+
+def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, stream=None):
+    """Returns (status, iterations, relative residual); status OK or ENOCONV."""
+    it = _i32()
+    rr = _f64()
+    code = _lib.pcg_solve(A.h, M.h, _ptr(b), _ptr(x), float(rtol), int(maxit), 1, C.byref(it), C.byref(rr),
+                          _stream(stream))
+    _check(code, "pcg_solve", allow=(OK, ENOCONV))
+    return code, it.value, rr.value

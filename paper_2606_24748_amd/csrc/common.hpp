@@ -1,0 +1,194 @@
+// Shared internals of libblkamg: error handling across the C ABI, device buffers,
+// value-type helpers, launch geometry for gfx950 and wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/blkamg.h"
+
+namespace blk {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws Error; every exported function catches at the
+// boundary, records the message and returns the status code.
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void set_last_error(const std::string& msg);
+
+#define BLK_REQUIRE(cond, code, msg)                      \
+  do {                                                    \
+    if (!(cond)) ::blk::fail((code), std::string(msg));   \
+  } while (0)
+
+#define HIP_CHECK(expr)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      ::blk::fail(e_ == hipErrorOutOfMemory ? BLKAMG_ENOMEM : BLKAMG_EHIP,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+// Wrap the body of an exported function.
+#define BLK_API_BEGIN try {
+#define BLK_API_END                                              \
+  return BLKAMG_OK;                                              \
+  }                                                              \
+  catch (const ::blk::Error& e) {                                \
+    ::blk::set_last_error(e.msg);                                \
+    return e.code;                                               \
+  }                                                              \
+  catch (const std::bad_alloc&) {                                \
+    ::blk::set_last_error("host allocation failed");             \
+    return BLKAMG_ENOMEM;                                        \
+  }                                                              \
+  catch (...) {                                                  \
+    ::blk::set_last_error("unexpected internal error");          \
+    return BLKAMG_EINVAL;                                        \
+  }
+
+// ---------------------------------------------------------------------------
+// Device buffer (owning, hipMalloc'd, freed on destruction)
+// ---------------------------------------------------------------------------
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(BLKAMG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    p = static_cast<T*>(q);
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+template <class T>
+inline void upload(DevBuf<T>& d, const std::vector<T>& h) {
+  d.alloc(h.size());
+  if (!h.empty()) HIP_CHECK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+inline std::vector<T> download(const T* d, size_t n) {
+  std::vector<T> h(n);
+  if (n) HIP_CHECK(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+  return h;
+}
+
+inline size_t dtype_size(int dt) {
+  switch (dt) {
+    case BLKAMG_F64: return 8;
+    case BLKAMG_F32: return 4;
+    case BLKAMG_BF16: return 2;
+    default: fail(BLKAMG_EINVAL, "unknown dtype " + std::to_string(dt));
+  }
+}
+
+// bfloat16 stored as raw 16 bits
+struct bf16 {
+  uint16_t bits;
+};
+
+__host__ __device__ inline float to_float(bf16 v) {
+  uint32_t u = static_cast<uint32_t>(v.bits) << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+// round-to-nearest-even float -> bf16 (NaN kept quiet)
+__host__ __device__ inline bf16 to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return bf16{static_cast<uint16_t>((u >> 16) | 0x40)};
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return bf16{static_cast<uint16_t>(u >> 16)};
+}
+
+template <class TA>
+__device__ __forceinline__ TA ld(const double* p) { return static_cast<TA>(*p); }
+template <class TA>
+__device__ __forceinline__ TA ld(const float* p) { return static_cast<TA>(*p); }
+template <class TA>
+__device__ __forceinline__ TA ld(const bf16* p) { return static_cast<TA>(to_float(*p)); }
+
+template <class T>
+__device__ __forceinline__ void st(T* p, double v) { *p = static_cast<T>(v); }
+template <class T>
+__device__ __forceinline__ void st(T* p, float v) { *p = static_cast<T>(v); }
+
+// ---------------------------------------------------------------------------
+// Launch geometry.  The hardware hands workgroup b to XCD (b mod 8); each XCD has
+// its own L2.  Remapping so that every XCD works on one contiguous range of
+// logical blocks keeps neighbouring block rows (which share gathered vector
+// entries) in the same L2.
+// ---------------------------------------------------------------------------
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int xcd_logical_block(int hw_block, int nblocks) {
+  const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+  const int x = hw_block % kNumXcd, k = hw_block / kNumXcd;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// sum over the G lanes of a group (G a power of two <= 64), result in all lanes
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// Deterministic sum over a 256-thread block; every thread contributes v, thread 0
+// gets the result (fixed order: wave tree, then the 4 waves in order).
+__device__ __forceinline__ double block_sum_256(double v, double* lds4) {
+  v = group_sum<64>(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds4[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  return s;
+}
+
+hipStream_t as_stream(void* s);
+
+}  // namespace blk

@@ -1,0 +1,65 @@
+// Internal object definitions shared by the translation units of libblkamg.
+#pragma once
+
+#include "common.hpp"
+
+struct bsr_s;
+
+namespace blk {
+
+// Cached explicit transpose R = A^T (pattern built once on the host; values
+// refreshed on the device whenever the owner's value stamp moved).
+struct TransposeCache {
+  DevBuf<int32_t> rowptr, colidx, map;  // map[t] = block of A copied (transposed) into R block t
+  DevBuf<char> val;
+  uint64_t stamp = 0;                   // owner stamp the values were copied at (0 = never)
+  std::unique_ptr<bsr_s> R;             // view over the arrays above
+};
+
+}  // namespace blk
+
+struct bsr_s {
+  int32_t nbr = 0, nbc = 0, br = 0, bc = 0;
+  int64_t nnzb = 0;
+  int dtype = BLKAMG_F64;
+  const int32_t* rowptr = nullptr;
+  const int32_t* colidx = nullptr;
+  void* val = nullptr;
+  // owned storage (library-created matrices)
+  blk::DevBuf<int32_t> own_rowptr, own_colidx;
+  blk::DevBuf<char> own_val;
+  uint64_t stamp = 1;  // value-state stamp
+  std::unique_ptr<blk::TransposeCache> tcache;
+  // host copy of the pattern (filled on demand or at creation)
+  std::vector<int32_t> h_rowptr, h_colidx;
+  bool h_pattern = false;
+  // plan attached by ptap_symbolic to the coarse matrix it creates
+  std::shared_ptr<void> ext;
+
+  size_t block_elems() const { return static_cast<size_t>(br) * bc; }
+  size_t val_bytes() const { return static_cast<size_t>(nnzb) * block_elems() * blk::dtype_size(dtype); }
+  double avg_blocks_per_row() const { return nbr ? static_cast<double>(nnzb) / nbr : 0.0; }
+};
+
+namespace blk {
+
+// Library-owned matrix with the given host pattern (uploaded) and zeroed values.
+std::unique_ptr<bsr_s> make_owned(int32_t nbr, int32_t nbc, int32_t br, int32_t bc, int dtype,
+                                  std::vector<int32_t> h_rowptr, std::vector<int32_t> h_colidx);
+// Make sure A->h_rowptr / h_colidx hold the pattern (downloads once; sync).
+void ensure_host_pattern(bsr_s* A);
+// Transpose cache of A, built if needed; values refreshed on `s` if stale.
+bsr_s* transpose_of(bsr_s* A, hipStream_t s);
+// y = alpha op(A) x + beta y
+void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs,
+          hipStream_t s);
+// Number of lanes cooperating on one block row.
+int lanes_for(const bsr_s* A);
+// Structural product of two host block patterns (sorted rows, no dropping).
+void structural_product_host(int32_t nra, const std::vector<int32_t>& rpa, const std::vector<int32_t>& cia,
+                             int32_t ncb, const std::vector<int32_t>& rpb, const std::vector<int32_t>& cib,
+                             std::vector<int32_t>& rpc, std::vector<int32_t>& cic);
+// Cast a value array between dtypes on the device.
+void cast_values(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
+
+}  // namespace blk

@@ -1,0 +1,125 @@
+// Blocked SpMV core for gfx950 (paper §4.2: one index per dense block).
+//
+// A group of G lanes (G a power of two dividing the 64-lane wavefront) owns one
+// block row.  Lane l takes blocks k0+l, k0+l+G, ... of the row: consecutive lanes
+// read consecutive blocks, so a wave's value loads cover one contiguous stretch of
+// the value array.  Each lane keeps one whole block in registers, gathers the
+// BC*NRHS entries of x it multiplies, and accumulates BR*NRHS partial sums; the
+// group then reduces them with cross-lane shuffles (no LDS, no atomics), so the
+// result is deterministic.  The per-row epilogue is a template parameter, which
+// lets the smoother, residual and CG kernels fuse their vector updates into the
+// product instead of making extra passes over HBM.
+#pragma once
+
+#include "internal.hpp"
+
+namespace blk {
+
+constexpr int kBlock = 256;
+
+template <class T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) { return a * b + c; }
+
+template <int N, class T>
+__device__ __forceinline__ T pick(const T (&v)[N], int i) {
+  T r = T(0);
+#pragma unroll
+  for (int t = 0; t < N; ++t)
+    if (t == i) r = v[t];
+  return r;
+}
+
+template <int BR, int BC, int NR, int G, class TM, class TX, class TA>
+__device__ __forceinline__ void row_product(const int32_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ colidx,
+                                            const TM* __restrict__ val, const TX* __restrict__ x,
+                                            int row, int lane, TA (&acc)[BR * NR]) {
+#pragma unroll
+  for (int t = 0; t < BR * NR; ++t) acc[t] = TA(0);
+  const int k0 = rowptr[row], k1 = rowptr[row + 1];
+  for (int k = k0 + lane; k < k1; k += G) {
+    const int c = colidx[k];
+    const TX* xc = x + static_cast<size_t>(c) * (BC * NR);
+    TA xv[BC * NR];
+#pragma unroll
+    for (int t = 0; t < BC * NR; ++t) xv[t] = ld<TA>(xc + t);
+    const TM* b = val + static_cast<size_t>(k) * (BR * BC);
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+#pragma unroll
+      for (int j = 0; j < BC; ++j) {
+        const TA a = ld<TA>(b + i * BC + j);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[i * NR + q] = fmadd(a, xv[j * NR + q], acc[i * NR + q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < BR * NR; ++t) acc[t] = group_sum<G>(acc[t]);
+}
+
+// Generic kernel: every thread calls the epilogue (it may hold block-wide reductions).
+template <int BR, int BC, int NR, int G, class TM, class TX, class TA, class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colidx,
+                                                      const TM* __restrict__ val,
+                                                      const TX* __restrict__ x, Epi epi) {
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
+  const int lane = static_cast<int>(threadIdx.x) % G;
+  TA acc[BR * NR];
+  const bool active = row < nbr;
+  if (active) {
+    row_product<BR, BC, NR, G, TM, TX, TA>(rowptr, colidx, val, x, row, lane, acc);
+  } else {
+#pragma unroll
+    for (int t = 0; t < BR * NR; ++t) acc[t] = TA(0);
+  }
+  epi.template apply<BR, NR, G>(active, lb, row, lane, acc);
+}
+
+template <int G>
+inline int grid_for_rows(int nbr) { return ceil_div(nbr, kBlock / G); }
+
+// Launch spmv_kernel with G chosen at run time from {8, 16, 32, 64}.
+template <int BR, int BC, int NR, class TM, class TX, class TA, class Epi>
+void launch_rows(int G, int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val,
+                 const TX* x, const Epi& epi, hipStream_t s) {
+  if (nbr <= 0) return;
+  switch (G) {
+    case 8:
+      spmv_kernel<BR, BC, NR, 8, TM, TX, TA, Epi><<<grid_for_rows<8>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+      break;
+    case 16:
+      spmv_kernel<BR, BC, NR, 16, TM, TX, TA, Epi><<<grid_for_rows<16>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+      break;
+    case 32:
+      spmv_kernel<BR, BC, NR, 32, TM, TX, TA, Epi><<<grid_for_rows<32>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+      break;
+    default:
+      spmv_kernel<BR, BC, NR, 64, TM, TX, TA, Epi><<<grid_for_rows<64>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+      break;
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+inline int grid_for(int G, int nbr) { return ceil_div(nbr, kBlock / G); }
+
+// y = alpha * (A x) + beta * y
+template <class TY, class TA>
+struct EpiAxpby {
+  TY* __restrict__ y;
+  TA alpha, beta;
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ void apply(bool active, int, int row, int lane, const TA (&acc)[BR * NR]) const {
+    if (!active) return;
+    for (int l = lane; l < BR * NR; l += G) {
+      const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
+      TA v = alpha * pick(acc, l);
+      if (beta != TA(0)) v = fmadd(beta, ld<TA>(y + o), v);
+      st(y + o, v);
+    }
+  }
+};
+
+}  // namespace blk

@@ -1,0 +1,79 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry
+point, and its host-only aggregation reproduces the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sparse as S
+from oracle import sa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+B = pytest.importorskip("paper_2606_24748_amd.blkamg", reason="libblkamg.so not built")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "blkamg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names) - {"if", "while"})
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(B._lib, n), n
+    assert sorted(B.exported_symbols()) == names
+
+
+def test_version_and_last_error():
+    assert B._lib.blkamg_version() >= 100
+    assert isinstance(B._lib.blkamg_last_error(), bytes)
+
+
+def _mesh_operator(n, seed=None):
+    m = synth.make_mesh(n)
+    i, j = synth.coo_indices(m)
+    E, nu = synth.homogeneous_materials(m.n_elem) if seed is None else synth.materials(m.n_elem, seed)
+    A = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, synth.coo_values(m, *synth.lame(E, nu)))
+    return m, A
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 5, 8, 11, 16])
+def test_host_aggregation_bit_exact_vs_oracle(n):
+    m, A = _mesh_operator(n)
+    agg, n_agg = B.sa_aggregate(A.rowptr, A.colidx, m.dirichlet)
+    want, n_want = sa.aggregate(sa.strength_graph(A, m.dirichlet), m.dirichlet)
+    assert n_agg == n_want
+    assert np.array_equal(agg, want)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_host_aggregation_random_graphs(seed):
+    rp, ci, _ = synth.random_spd_bsr(60, 1, seed=seed, max_per_row=3)
+    rng = np.random.default_rng(seed)
+    dmask = rng.random(60) < 0.1
+    A = S.Bsr(60, 60, 1, 1, rp.astype(np.int64), ci.astype(np.int64), np.zeros((len(ci), 1, 1)))
+    agg, n_agg = B.sa_aggregate(rp, ci, dmask)
+    want, n_want = sa.aggregate(sa.strength_graph(A, dmask), dmask)
+    assert n_agg == n_want and np.array_equal(agg, want)
+
+
+def test_host_aggregation_rejects_bad_pattern():
+    with pytest.raises(B.BlkAmgError) as e:
+        B.sa_aggregate(np.array([0, 1]), np.array([5]))
+    assert e.value.code == B.EINVAL
+    agg, n = B.sa_aggregate(np.array([0]), np.array([], dtype=np.int32))
+    assert n == 0 and len(agg) == 0
+
+
+def test_default_options():
+    o = B.blkamg_opts_default()
+    assert (o.max_levels, o.coarse_eq_limit, o.cheb_degree, o.lanczos_steps) == (10, 1000, 2, 10)
+    assert (o.cheb_lo, o.cheb_hi, o.strength_eps) == (0.1, 1.1, 0.0)
+    assert o.lanczos_seed == 0x5EED and abs(o.omega_scale - 4 / 3) < 1e-15

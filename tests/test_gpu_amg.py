@@ -1,0 +1,124 @@
+"""GPU parity of the hierarchy, smoother, V-cycle and PCG against the CPU oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import sparse as S  # noqa: E402
+from oracle import solve  # noqa: E402
+from paper_2606_24748_amd import blkamg as B  # noqa: E402
+from tests.gpu_util import dev, from_device_bsr, q1_problem, rel2  # noqa: E402
+
+
+def _gpu_problem(n, mat_seed=None, hier=B.F64, pdt=B.F64):
+    m, i, j, v, A = q1_problem(n, mat_seed)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    vals = dev(v)
+    B.coo_assemble_blocked(plan, vals, B.INSERT, HA)
+    o = B.blkamg_opts_default()
+    o.hier_dtype = hier
+    o.p_dtype = pdt
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    return m, i, j, A, plan, HA, M
+
+
+@pytest.mark.parametrize("n,seed", [(8, None), (12, 3)])
+def test_setup_matches_oracle(n, seed):
+    print(f"setup n={n} seed={seed}", flush=True)
+    m, i, j, A, plan, HA, M = _gpu_problem(n, seed)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    assert M.num_levels() == H.n_levels
+    lam = M.lambdas()
+    for l in range(H.n_levels - 1):
+        L = H.levels[l]
+        assert np.array_equal(M.aggregates(l), L.agg)
+        assert abs(lam[l] - L.lam) <= 1e-12 * L.lam
+        _, HP = M.level(l)
+        P = from_device_bsr(HP)
+        assert np.array_equal(P.rowptr, L.P.rowptr) and np.array_equal(P.colidx, L.P.colidx)
+        assert rel2(P.val, L.P.val) <= 1e-12
+        HAc, _ = M.level(l + 1)
+        Ac = from_device_bsr(HAc)
+        want = H.levels[l + 1].A
+        assert np.array_equal(Ac.rowptr, want.rowptr) and np.array_equal(Ac.colidx, want.colidx)
+        assert rel2(Ac.val, want.val) <= 1e-12
+
+
+def test_vcycle_matches_oracle_f64():
+    m, i, j, A, plan, HA, M = _gpu_problem(8, 5)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    r = np.random.default_rng(0).uniform(-1, 1, m.n_dof)
+    z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, dev(r), z)
+    assert rel2(z.cpu().numpy(), solve.vcycle(H, r)) <= 1e-11
+
+
+@pytest.mark.parametrize("n,seed", [(8, None), (16, 1)])
+def test_pcg_iterations_and_residual(n, seed):
+    print(f"pcg n={n}", flush=True)
+    m, i, j, A, plan, HA, M = _gpu_problem(n, seed)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    b = synth.rhs(m, 2)
+    _, it_o, rel_o, ok = solve.pcg(A, b, lambda r: solve.vcycle(H, r), rtol=1e-8)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
+    assert code == B.OK and ok
+    assert abs(it - it_o) <= 1
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - S.spmv(A, xs)) <= 2e-8 * np.linalg.norm(b)
+    assert rel <= 1e-8
+
+
+def test_hot_recompute_matches_oracle():
+    m, i, j, A, plan, HA, M = _gpu_problem(10, 7)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    E, nu = synth.materials(m.n_elem, 1007)
+    v2 = synth.coo_values(m, *synth.lame(E, nu))
+    B.coo_assemble_blocked(plan, dev(v2), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    B.amg_smoother_refresh(M)
+    A2 = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v2)
+    H2 = solve.recompute(H, A2)
+    lam = M.lambdas()
+    for l in range(H2.n_levels - 1):
+        assert abs(lam[l] - H2.levels[l].lam) <= 1e-12 * H2.levels[l].lam
+        Ac = from_device_bsr(M.level(l + 1)[0])
+        assert rel2(Ac.val, H2.levels[l + 1].A.val) <= 1e-12
+    b = synth.rhs(m, 3)
+    _, it_o, _, _ = solve.pcg(A2, b, lambda r: solve.vcycle(H2, r), rtol=1e-8)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x)
+    assert code == B.OK and abs(it - it_o) <= 1
+
+
+def test_pcg_zero_rhs_maxit_and_user_lambda():
+    m, i, j, A, plan, HA, M = _gpu_problem(6, 2)
+    x = torch.ones(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, torch.zeros(m.n_dof, dtype=torch.float64, device="cuda"), x)
+    assert code == B.OK and it == 0 and not torch.any(x)
+    b = dev(synth.rhs(m, 1))
+    code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-14, maxit=2)
+    assert code == B.ENOCONV and it == 2
+    lam = M.lambdas()
+    B.amg_smoother_refresh(M, lam * 1.5)
+    assert np.allclose(M.lambdas(), lam * 1.5, rtol=1e-15)
+
+
+@pytest.mark.parametrize("pdt", [B.F32, B.BF16])
+def test_f32_hierarchy_converges(pdt):
+    m, i, j, A, plan, HA, M = _gpu_problem(12, 4, hier=B.F32, pdt=pdt)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    b = synth.rhs(m, 5)
+    _, it_o, _, _ = solve.pcg(A, b, lambda r: solve.vcycle(H, r), rtol=1e-8)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
+    assert code == B.OK
+    assert it <= it_o + 3
+    assert np.linalg.norm(b - S.spmv(A, x.cpu().numpy())) <= 2e-8 * np.linalg.norm(b)
+    # the FP32 coarse operators agree with the FP64 oracle to FP32 accuracy
+    for l in range(H.n_levels - 1):
+        Ac = from_device_bsr(M.level(l + 1)[0])
+        assert rel2(Ac.val, H.levels[l + 1].A.val) <= (1e-5 if pdt == B.F32 else 2e-2)

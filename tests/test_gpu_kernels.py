@@ -1,0 +1,174 @@
+"""GPU parity of the sparse kernels (SpMV, SpMV-transpose, blocked COO, Galerkin
+product) against the CPU oracle, called through the C ABI."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import sparse as S  # noqa: E402
+from paper_2606_24748_amd import blkamg as B  # noqa: E402
+from tests.gpu_util import dev, from_device_bsr, q1_problem, rel2, to_device_bsr  # noqa: E402
+
+
+def _rand(nbr, nbc, br, bc, seed, **kw):
+    rp, ci, v = synth.random_bsr(nbr, nbc, br, bc, seed, **kw)
+    return S.Bsr(nbr, nbc, br, bc, rp.astype(np.int64), ci.astype(np.int64), v)
+
+
+SHAPES = [(3, 3, 30), (3, 6, 6), (6, 3, 60), (6, 6, 30), (2, 5, 7), (1, 1, 9)]
+
+
+@pytest.mark.parametrize("br,bc,per_row", SHAPES)
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_spmv_f64_random(br, bc, per_row, nrhs):
+    print(f"spmv f64 {br}x{bc} nrhs={nrhs}", flush=True)
+    A = _rand(1037, 611, br, bc, seed=br * 7 + bc, max_per_row=per_row, empty_row_frac=0.05)
+    H, keep = to_device_bsr(A)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, (A.nbc * bc, nrhs))
+    y0 = rng.uniform(-1, 1, (A.nbr * br, nrhs))
+    want = S.spmv(A, x, 0.75, -0.5, y0)
+    y = dev(y0)
+    B.bsr_spmv(H, 0.75, dev(x), -0.5, y, nrhs=nrhs)
+    assert rel2(y.cpu().numpy(), want) <= 1e-12
+    # beta = 0 overwrites (NaN in y ignored)
+    y = torch.full((A.nbr * br, nrhs), float("nan"), dtype=torch.float64, device="cuda")
+    B.bsr_spmv(H, 1.0, dev(x), 0.0, y, nrhs=nrhs)
+    assert rel2(y.cpu().numpy(), S.spmv(A, x)) <= 1e-12
+    # transpose through the cached explicit transpose
+    xt = rng.uniform(-1, 1, (A.nbr * br, nrhs))
+    yt = torch.zeros((A.nbc * bc, nrhs), dtype=torch.float64, device="cuda")
+    B.bsr_spmv_t(H, 1.0, dev(xt), 0.0, yt, nrhs=nrhs)
+    assert rel2(yt.cpu().numpy(), S.spmv_t(A, xt)) <= 1e-12
+
+
+def test_spmv_transpose_cache_follows_value_stamp():
+    A = _rand(300, 200, 3, 6, seed=5, max_per_row=5)
+    H, (rp, ci, v) = to_device_bsr(A)
+    x = np.random.default_rng(2).uniform(-1, 1, A.nbr * 3)
+    y = torch.zeros(A.nbc * 6, dtype=torch.float64, device="cuda")
+    B.bsr_spmv_t(H, 1.0, dev(x), 0.0, y)
+    assert rel2(y.cpu().numpy(), S.spmv_t(A, x)) <= 1e-12
+    v.mul_(-2.0)
+    B.bsr_mark_modified(H)
+    B.bsr_spmv_t(H, 1.0, dev(x), 0.0, y)
+    assert rel2(y.cpu().numpy(), -2.0 * S.spmv_t(A, x)) <= 1e-12
+
+
+@pytest.mark.parametrize("br,bc", [(3, 3), (3, 6), (6, 6)])
+def test_spmv_f32_and_bf16(br, bc):
+    A = _rand(800, 500, br, bc, seed=11, max_per_row=20)
+    x = np.random.default_rng(3).uniform(-1, 1, A.nbc * bc)
+    want = S.spmv(A, x)
+    H32, _ = to_device_bsr(A, B.F32)
+    y = torch.zeros(A.nbr * br, dtype=torch.float32, device="cuda")
+    B.bsr_spmv(H32, 1.0, dev(x, torch.float32), 0.0, y)
+    assert rel2(y.cpu().numpy(), want) <= 2e-6
+    if bc == 6:
+        H16, _ = to_device_bsr(A, B.BF16)
+        B.bsr_spmv(H16, 1.0, dev(x, torch.float32), 0.0, y)
+        assert rel2(y.cpu().numpy(), want) <= 1e-2
+        # exact w.r.t. the rounded values
+        Ab = A.with_values(torch.as_tensor(A.val).to(torch.bfloat16).to(torch.float64).numpy())
+        xf = torch.as_tensor(x).to(torch.float32).to(torch.float64).numpy()
+        assert rel2(y.cpu().numpy(), S.spmv(Ab, xf)) <= 2e-6
+
+
+def test_spmv_empty_and_errors():
+    A = S.Bsr(5, 4, 3, 3, np.zeros(6, np.int64), np.zeros(0, np.int64), np.zeros((0, 3, 3)))
+    H, _ = to_device_bsr(A)
+    y = torch.ones(15, dtype=torch.float64, device="cuda")
+    B.bsr_spmv(H, 1.0, torch.zeros(12, dtype=torch.float64, device="cuda"), 2.0, y)
+    assert torch.all(y == 2.0)
+    with pytest.raises(B.BlkAmgError) as e:
+        B.bsr_spmv(H, 1.0, torch.zeros(12, device="cuda"), 0.0, torch.zeros(15, device="cuda"))
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BlkAmgError):
+        B.bsr_spmv(H, 1.0, torch.zeros(12, dtype=torch.float64, device="cuda"), 0.0, y, nrhs=9)
+
+
+def test_coo_plan_bit_exact_and_values():
+    nbr, nbc = 257, 131
+    i, j, v = synth.random_coo_stream(nbr, nbc, 3, 6, 20000, seed=4, neg_frac=0.1, dup_pool=3000)
+    plan, H = B.coo_plan_create(nbr, nbc, 3, 6, i, j)
+    rp, ci, perm, seg = S.coo_plan(nbr, nbc, i, j)
+    dperm, dseg = plan.index_map()
+    assert np.array_equal(dperm.cpu().numpy(), perm)
+    assert np.array_equal(dseg.cpu().numpy(), seg)
+    got_rp, got_ci, _ = H.arrays()
+    assert np.array_equal(got_rp.cpu().numpy(), rp) and np.array_equal(got_ci.cpu().numpy(), ci)
+    vals = dev(v)
+    B.coo_assemble_blocked(plan, vals, B.INSERT, H)
+    A = S.coo_assemble(nbr, nbc, i, j, v)
+    got = from_device_bsr(H)
+    assert np.array_equal(got.val, A.val)       # same summation order: identical bits
+    B.coo_assemble_blocked(plan, vals, B.ADD, H)
+    assert np.array_equal(from_device_bsr(H).val, 2 * A.val)
+    with pytest.raises(B.BlkAmgError):
+        B.coo_plan_create(nbr, nbc, 3, 6, np.array([nbr], np.int32), np.array([0], np.int32))
+
+
+def test_coo_elasticity_stream_tiny_and_empty():
+    m, i, j, v, A = q1_problem(8)
+    plan, H = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, H)
+    got = from_device_bsr(H)
+    assert np.array_equal(got.rowptr, A.rowptr) and np.array_equal(got.colidx, A.colidx)
+    assert got.nnzb == 13831
+    assert np.array_equal(got.val, A.val)
+    plan0, H0 = B.coo_plan_create(4, 4, 3, 3, np.array([-1, -1], np.int32), np.array([-1, 2], np.int32))
+    B.coo_assemble_blocked(plan0, dev(np.zeros((2, 3, 3))), B.INSERT, H0)
+    assert H0.info()["nnzb"] == 0
+
+
+def test_ptap_random_against_oracle_and_stamp_gating():
+    rp, ci, v = synth.random_spd_bsr(400, 3, seed=9, max_per_row=12)
+    A = S.Bsr(400, 400, 3, 3, rp.astype(np.int64), ci.astype(np.int64), v)
+    P = _rand(400, 57, 3, 6, seed=10, max_per_row=4)
+    HA, _ = to_device_bsr(A)
+    HP, (prp, pci, pv) = to_device_bsr(P)
+    HC = B.ptap_symbolic(HA, HP)
+    B.ptap_numeric(HA, HP, HC)
+    want = S.ptap(A, P)
+    got = from_device_bsr(HC)
+    assert np.array_equal(got.rowptr, want.rowptr) and np.array_equal(got.colidx, want.colidx)
+    assert rel2(got.val, want.val) <= 1e-12
+    # new prolongator values: gated refresh of the cached transpose
+    pv.mul_(0.5)
+    B.bsr_mark_modified(HP)
+    B.ptap_numeric(HA, HP, HC)
+    assert rel2(from_device_bsr(HC).val, 0.25 * want.val) <= 1e-12
+    # same values again: deterministic bits
+    first = from_device_bsr(HC).val.copy()
+    B.ptap_numeric(HA, HP, HC)
+    assert np.array_equal(from_device_bsr(HC).val, first)
+
+
+def test_ptap_coarse_6x6_and_f32():
+    rp, ci, v = synth.random_spd_bsr(200, 6, seed=3, max_per_row=10)
+    A = S.Bsr(200, 200, 6, 6, rp.astype(np.int64), ci.astype(np.int64), v)
+    P = _rand(200, 31, 6, 6, seed=12, max_per_row=3)
+    HA, _ = to_device_bsr(A)
+    HP, _ = to_device_bsr(P)
+    HC = B.ptap_symbolic(HA, HP)
+    B.ptap_numeric(HA, HP, HC)
+    want = S.ptap(A, P)
+    assert rel2(from_device_bsr(HC).val, want.val) <= 1e-12
+    HA32, _ = to_device_bsr(A, B.F32)
+    HP32, _ = to_device_bsr(P, B.F32)
+    HC32 = B.ptap_symbolic(HA32, HP32)
+    B.ptap_numeric(HA32, HP32, HC32)
+    assert rel2(from_device_bsr(HC32).val, want.val) <= 1e-5
+
+
+def test_ptap_errors():
+    A = _rand(10, 10, 3, 3, seed=1)
+    P = _rand(11, 4, 3, 6, seed=2)
+    HA, _ = to_device_bsr(A)
+    HP, _ = to_device_bsr(P)
+    with pytest.raises(B.BlkAmgError) as e:
+        B.ptap_symbolic(HA, HP)
+    assert e.value.code == B.EINVAL
