@@ -1,0 +1,323 @@
+#!/usr/bin/env python3
+"""Benchmark of the blocked SA-AMG solve phase on one MI355X.
+
+Workload: Q1 hexahedral linear elasticity on the unit cube with 128^3 elements
+(6,440,067 dofs, 3x3 blocks), per-element E ~ lognormal(0, 1) and nu ~ U[0.2, 0.35]
+(material seed 11, redraw seed 1011), right-hand side U[-1, 1] (seed 12), x = 0 face
+clamped; 4-level smoothed-aggregation hierarchy (3x3 fine, 3x6 / 6x6 prolongators,
+6x6 coarse operators), Chebyshev(2)/point-block-Jacobi V-cycle inside CG to a
+relative residual of 1e-8.
+
+One step = one pass of the hot path on fresh operator values: blocked COO assembly of
+the fine operator, Galerkin recompute A_c = P^T A P on every level (fixed patterns,
+reused prolongators), smoother refresh (block-diagonal inverses, Lanczos estimates,
+coarsest Cholesky), and the PCG solve.  Values alternate between two material draws,
+so every step really recomputes.  Two hierarchies are timed: "mixed" (V-cycle
+hierarchy in FP32 with FP32 accumulation; FP64 PCG, fine residual SpMV and coarsest
+Cholesky) and "fp64".  The reported value is PCG solve seconds + PtAP recompute
+seconds of the mixed hierarchy (median over the timed steps); the FP64 figures are
+reported beside it.
+
+Also reported: the HBM roofline of the fine 3x3 FP64 SpMV (bsr_spmv) measured with
+HIP events, the Galerkin recompute's algorithmic bandwidth, and the CPU oracle timed
+on this host on a bounded sample (see cpu_baseline.sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PCG solve s + PtAP recompute s at 128^3 elasticity; %HBM peak; mixed vs FP64"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="elements per cube edge")
+    ap.add_argument("--variants", default="mixed,fp64", help="comma list of mixed, mixed-bf16, fp64")
+    ap.add_argument("--probe-reps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="only assemble the fine operator and run the SpMV probe and the copy calibration")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-n", type=int, default=32, help=argparse.SUPPRESS)
+    return ap.parse_args(argv)
+
+
+# ----------------------------------------------------------------------------------
+# CPU baseline: the oracle, single core, on a bounded sample (run in a child process)
+# ----------------------------------------------------------------------------------
+def cpu_baseline_child(n: int) -> dict:
+    try:
+        cpus = sorted(os.sched_getaffinity(0))
+        os.sched_setaffinity(0, {cpus[0]})
+    except (AttributeError, OSError):
+        pass
+    import numpy as np
+
+    import synth
+    from oracle import solve
+    from oracle import sparse as S
+
+    m = synth.make_mesh(n)
+    i, j = synth.coo_indices(m)
+    v0 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 11)))
+    v1 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 1011)))
+    A0 = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v0)
+    H = solve.setup(A0, m.coords, m.dirichlet)
+    t0 = time.perf_counter()
+    A1 = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v1)
+    t_coo = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    A = A1
+    for L in H.levels[:-1]:
+        A = S.ptap(A, L.P)
+    t_ptap = time.perf_counter() - t0
+    H1 = solve.recompute(H, A1)
+    b = synth.rhs(m, 12)
+    t0 = time.perf_counter()
+    _, its, rel, ok = solve.pcg(A1, b, lambda r: solve.vcycle(H1, r), rtol=1e-8)
+    t_pcg = time.perf_counter() - t0
+    return {"n": n, "nnzb": int(A1.nnzb), "coo_s": t_coo, "ptap_s": t_ptap, "pcg_s": t_pcg, "pcg_its": its,
+            "converged": bool(ok), "relres": rel, "host_cpus": os.cpu_count()}
+
+
+def run_cpu_baseline(n: int) -> dict | None:
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-n", str(n)]
+    try:
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=300)
+    except subprocess.TimeoutExpired:
+        log("cpu baseline timed out")
+        return None
+    if r.returncode != 0:
+        log("cpu baseline failed: " + r.stderr[-2000:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# ----------------------------------------------------------------------------------
+# GPU benchmark
+# ----------------------------------------------------------------------------------
+def spmv_probe(B, RL, torch, plan, HA, vals0, n_dof, a_inf, reps, stream):
+    """Average duration of the fine 3x3 FP64 bsr_spmv, timed with HIP events on the
+    stream it is launched on, and its algorithmic bandwidth."""
+    B.coo_assemble_blocked(plan, vals0, B.INSERT, HA)
+    xv = torch.rand(n_dof, dtype=torch.float64, device="cuda")
+    yv = torch.zeros(n_dof, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        B.bsr_spmv(HA, 1.0, xv, 0.0, yv)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        B.bsr_spmv(HA, 1.0, xv, 0.0, yv)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = RL.spmv_bytes(a_inf["nbr"], a_inf["nbc"], 3, 3, a_inf["nnzb"], 8, 8)
+    return {"avg_launch_ms": ms, "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+            "reps": reps}
+
+
+def copy_probe(torch, stream, nbytes=1 << 30, reps=10):
+    """A plain streaming kernel of known size (y = -x, 8-byte elements: nbytes read and
+    nbytes written per launch), used to scale hardware byte counters."""
+    x = torch.rand(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "avg_launch_ms": ms,
+            "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_child(args.cpu_n)))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this solve-phase build has no "
+              "multi-GPU path", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_24748_amd import blkamg as B
+    from paper_2606_24748_amd import roofline as RL
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n = args.n
+    t_all = time.perf_counter()
+    mesh = synth.make_mesh(n)
+    ii, jj = synth.coo_indices(mesh)
+    mats = [synth.lame(*synth.materials(mesh.n_elem, 11)), synth.lame(*synth.materials(mesh.n_elem, 1011))]
+    vals = [synth.coo_values_torch(mesh, lam, mu, dev) for lam, mu in mats]
+    b = torch.as_tensor(synth.rhs(mesh, 12), device=dev)
+    log(f"inputs ready: n={n} dofs={mesh.n_dof} n_coo={len(ii)} ({time.perf_counter() - t_all:.1f}s)")
+
+    t0 = time.perf_counter()
+    plan, HA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, ii, jj)
+    t_plan = time.perf_counter() - t0
+    a_inf = HA.info()
+    log(f"coo plan: nnzb={a_inf['nnzb']} ({t_plan:.1f}s)")
+    del ii, jj
+
+    stream = torch.cuda.current_stream()
+    if args.probe_only:
+        probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+        probe["copy"] = copy_probe(torch, stream)
+        print(json.dumps({"probe": probe, "n": n}))
+        return 0
+    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    results = {}
+    for var in variants:
+        o = B.blkamg_opts_default()
+        if var == "fp64":
+            o.hier_dtype, o.p_dtype = B.F64, B.F64
+        elif var == "mixed":
+            o.hier_dtype, o.p_dtype = B.F32, B.F32
+        elif var == "mixed-bf16":
+            o.hier_dtype, o.p_dtype = B.F32, B.BF16
+        else:
+            raise SystemExit(f"unknown variant {var}")
+        B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
+        t_setup = time.perf_counter() - t0
+        nl = M.num_levels()
+        lev = []
+        for l in range(nl):
+            Al, Pl = M.level(l)
+            ai = Al.info()
+            lev.append({"nbr": ai["nbr"], "bs": ai["bs_r"], "nnzb": ai["nnzb"],
+                        "p_nnzb": Pl.info()["nnzb"] if Pl is not None else 0})
+        log(f"[{var}] setup {t_setup:.1f}s levels {[(d['nbr'] * d['bs'], d['nnzb']) for d in lev]}")
+        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev)
+        rec = []
+        for s in range(args.warmup + args.steps):
+            timed = s >= args.warmup
+            if s == args.warmup:
+                torch.cuda.synchronize()
+                t_region = time.perf_counter()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            vi = (s + 1) % 2
+            ev[0].record(stream)
+            B.coo_assemble_blocked(plan, vals[vi], B.INSERT, HA)
+            ev[1].record(stream)
+            B.amg_galerkin_recompute(M)
+            ev[2].record(stream)
+            B.amg_smoother_refresh(M)
+            ev[3].record(stream)
+            code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000)
+            ev[4].record(stream)
+            ev[4].synchronize()
+            ph = [ev[k].elapsed_time(ev[k + 1]) for k in range(4)]
+            if timed:
+                rec.append({"coo_ms": ph[0], "ptap_ms": ph[1], "refresh_ms": ph[2], "pcg_ms": ph[3], "its": its,
+                            "relres": rel, "status": code, "values": vi})
+            log(f"[{var}] step {s} {'timed' if timed else 'warmup'}: coo {ph[0]:.2f} ms, ptap {ph[1]:.2f} ms, "
+                f"refresh {ph[2]:.2f} ms, pcg {ph[3]:.1f} ms ({its} its, relres {rel:.2e})")
+        torch.cuda.synchronize()
+        region_s = time.perf_counter() - t_region
+        # true residual of the last solve with the FP64 fine operator (library SpMV)
+        r = b.clone()
+        B.bsr_spmv(HA, -1.0, x, 1.0, r)
+        true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+        med = {k: statistics.median(rr[k] for rr in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
+        # Galerkin recompute algorithmic bytes over all levels
+        vsz = 8 if o.hier_dtype == B.F64 else 4
+        psz = {B.F64: 8, B.F32: 4, B.BF16: 2}[o.p_dtype]
+        ptap_bytes = 0
+        for l in range(nl - 1):
+            d, c = lev[l], lev[l + 1]
+            ptap_bytes += RL.ptap_bytes(d["nbr"], d["nnzb"], d["bs"], d["p_nnzb"], 6, c["nbr"], c["nnzb"], vsz, psz)
+        if o.hier_dtype != B.F64:
+            ptap_bytes += a_inf["nnzb"] * 9 * (8 + 4)  # cast of the fine operator to the F32 copy
+        results[var] = {
+            "setup_s": t_setup, "levels": lev, "steps": rec, "median_ms": med,
+            "pcg_plus_ptap_s": (med["pcg_ms"] + med["ptap_ms"]) / 1e3,
+            "ms_per_step": region_s * 1e3 / max(args.steps, 1),
+            "iterations": [rr["its"] for rr in rec], "true_relres": true_rel,
+            "ptap_alg_GBs": ptap_bytes / (med["ptap_ms"] * 1e-3) / 1e9,
+            "ptap_alg_bytes": ptap_bytes,
+            "x_norm": float(torch.linalg.norm(x)),
+        }
+        results[var]["_x"] = x
+        del M
+        torch.cuda.synchronize()
+
+    probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+    achieved, spmv_b, spmv_ms = probe["achieved_GBs"], probe["bytes_per_launch"], probe["avg_launch_ms"]
+
+    head = "mixed" if "mixed" in results else variants[0]
+    hr = results[head]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, 1 core)")
+        cb = run_cpu_baseline(args.cpu_n)
+        if cb:
+            scale = a_inf["nnzb"] / cb["nnzb"]
+            gpu_its = statistics.median(hr["iterations"])
+            est = cb["ptap_s"] * scale + cb["pcg_s"] / max(cb["pcg_its"], 1) * gpu_its * scale
+            cpu = {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+                   "sample": (f"oracle (numpy/scipy FP64) on the {cb['n']}^3 instance of the same problem family "
+                              f"(nnzb {cb['nnzb']}): PtAP recompute {cb['ptap_s']:.2f} s, PCG {cb['pcg_s']:.2f} s "
+                              f"for {cb['pcg_its']} its; scaled linearly by fine nnzb (x{scale:.1f}) and to "
+                              f"{gpu_its} iterations"),
+                   "measured": cb}
+    for v in results.values():
+        v.pop("_x", None)
+    value = hr["pcg_plus_ptap_s"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head.startswith("mixed") else "f64", "data": "synthetic",
+        "config": {"workload": f"Q1 elasticity {n}^3 elements ({mesh.n_dof} dofs), lognormal E, "
+                               f"{len(hr['levels'])}-level SA, Chebyshev(2) V-cycle PCG to 1e-8",
+                   "n": n, "dofs": mesh.n_dof, "variant": head},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / RL.HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "bsr_spmv fine 3x3 f64 (spmv_kernel<3,3,1,32,double,double,double,EpiAxpby>)",
+                     "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
+        "cpu_baseline": cpu,
+        "variants": results,
+        "coo_plan_s": t_plan,
+    }
+    if "fp64" in results and head != "fp64":
+        out["fp64_value"] = results["fp64"]["pcg_plus_ptap_s"]
+        out["mixed_speedup_vs_fp64"] = results["fp64"]["pcg_plus_ptap_s"] / value
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -139,7 +139,7 @@ class Bsr:
         self._owner = owner
 
     def __del__(self):
-        if getattr(self, "_destroy", False) and self.h:
+        if getattr(self, "_destroy", False) and self.h and _lib is not None:
             _lib.bsr_destroy(self.h)
             self.h = None
 
@@ -225,7 +225,7 @@ class CooPlan:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.coo_plan_destroy(self.h)
             self.h = None
 
@@ -279,7 +279,7 @@ class Amg:
         self._keep = keep
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.amg_destroy(self.h)
             self.h = None
 

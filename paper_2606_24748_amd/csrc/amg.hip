@@ -262,7 +262,9 @@ struct EpiLanczos {
       for (int l = 0; l < BR * NR; ++l) {
         if ((l % G) != lane) continue;
         const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
-        const double w = static_cast<double>(s[l]) - bp * static_cast<double>(y_prev[o]);
+        // y_prev is not read on the first step (its buffer holds no data yet)
+        const double w = beta_prev ? static_cast<double>(s[l]) - bp * static_cast<double>(y_prev[o])
+                                   : static_cast<double>(s[l]);
         const TV wt = static_cast<TV>(w);
         wy[o] = wt;
         acc += static_cast<double>(u[o]) * static_cast<double>(wt);

@@ -17,6 +17,7 @@ from .q1 import (  # noqa: F401
     lame,
     coo_indices,
     coo_values,
+    coo_values_torch,
     rhs,
     stream_sizes,
 )

@@ -122,3 +122,30 @@ def test_f32_hierarchy_converges(pdt):
     for l in range(H.n_levels - 1):
         Ac = from_device_bsr(M.level(l + 1)[0])
         assert rel2(Ac.val, H.levels[l + 1].A.val) <= (1e-5 if pdt == B.F32 else 2e-2)
+
+
+@pytest.mark.parametrize("n", [12, 24])
+def test_f32_hierarchy_lambdas_and_recompute(n):
+    """FP32 Lanczos estimates agree with the FP64 oracle after setup and after a hot
+    recompute, and the V-cycle output stays finite (regression: the first Lanczos
+    step must not read the unset previous vector)."""
+    m, i, j, A, plan, HA, M = _gpu_problem(n, 6, hier=B.F32, pdt=B.F32)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    lam = M.lambdas()
+    assert np.all(np.isfinite(lam)) and np.all(lam > 0)
+    for l in range(H.n_levels - 1):
+        assert abs(lam[l] - H.levels[l].lam) <= 1e-4 * H.levels[l].lam
+    E, nu = synth.materials(m.n_elem, 1006)
+    v2 = synth.coo_values(m, *synth.lame(E, nu))
+    B.coo_assemble_blocked(plan, dev(v2), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    B.amg_smoother_refresh(M)
+    H2 = solve.recompute(H, S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v2))
+    lam = M.lambdas()
+    for l in range(H2.n_levels - 1):
+        assert abs(lam[l] - H2.levels[l].lam) <= 1e-4 * H2.levels[l].lam
+    r = np.random.default_rng(1).uniform(-1, 1, m.n_dof)
+    z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, dev(r), z)
+    zo = solve.vcycle(H2, r)
+    assert rel2(z.cpu().numpy(), zo) <= 1e-4
