@@ -50,6 +50,7 @@ struct amg_s {
   std::vector<std::unique_ptr<blk::Level>> lv;
   blk::DevBuf<blk::LevelScalars> sc;   // one per level
   blk::DevBuf<double> partial;         // block partial sums
+  blk::DevBuf<double> partial2;        // first-level chunk sums
   blk::DevBuf<double> pcg_s;           // PCG scalars
   blk::DevBuf<int> flags;              // [0] non-SPD pivot, [1] singular diagonal block
   // coarsest level dense data (F64)
@@ -70,6 +71,17 @@ namespace {
 // Deterministic reductions
 // ---------------------------------------------------------------------------
 enum RedOp { R_STORE = 0, R_SQRT, R_ALPHA, R_BETA };
+
+// first level: workgroup g sums the fixed chunk [g*chunk, (g+1)*chunk) of partials
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const double* __restrict__ partial, int n, int chunk,
+                                                            double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double v = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += 256) v += partial[i];
+  const double s = block_sum_256(v, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
 
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ partial, int n, double* dst, int op,
                                                      double* pcg) {
@@ -94,8 +106,18 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   }
 }
 
+// Deterministic sum of n partials (fixed chunking, fixed order), then `op`.
 void reduce(amg_s* M, int n, double* dst, int op, hipStream_t s) {
-  reduce_kernel<<<1, 256, 0, s>>>(M->partial.p, n, dst, op, M->pcg_s.p);
+  const double* src = M->partial.p;
+  if (n > 4096) {
+    const int chunks = 256;
+    const int chunk = (n + chunks - 1) / chunks;
+    reduce_chunks_kernel<<<chunks, 256, 0, s>>>(M->partial.p, n, chunk, M->partial2.p);
+    HIP_CHECK(hipGetLastError());
+    src = M->partial2.p;
+    n = chunks;
+  }
+  reduce_kernel<<<1, 256, 0, s>>>(src, n, dst, op, M->pcg_s.p);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -178,23 +200,22 @@ __global__ __launch_bounds__(256) void lanczos_start_kernel(int nbr, uint64_t se
                                                             const int32_t* __restrict__ diag_idx, TV* __restrict__ v,
                                                             TV* __restrict__ Dv, double* __restrict__ partial) {
   __shared__ double lds[4];
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   double acc = 0.0;
-  if (r < nbr) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nbr; r += gridDim.x * blockDim.x) {
     double vv[BS];
     for (int j = 0; j < BS; ++j) {
       const uint64_t z = splitmix64(seed ^ static_cast<uint64_t>(static_cast<int64_t>(r) * BS + j));
-      vv[j] = 2.0 * (static_cast<double>(z >> 11) * 0x1.0p-53) - 1.0;
+      vv[j] = static_cast<double>(static_cast<TV>(2.0 * (static_cast<double>(z >> 11) * 0x1.0p-53) - 1.0));
       v[static_cast<size_t>(r) * BS + j] = static_cast<TV>(vv[j]);
     }
     const int kd = diag_idx[r];
     for (int i = 0; i < BS; ++i) {
-      double s = 0.0;
+      double sv = 0.0;
       if (kd >= 0)
-        for (int j = 0; j < BS; ++j)
-          s += ld<double>(val + static_cast<size_t>(kd) * BS * BS + i * BS + j) * static_cast<double>(static_cast<TV>(vv[j]));
-      Dv[static_cast<size_t>(r) * BS + i] = static_cast<TV>(s);
-      acc += static_cast<double>(static_cast<TV>(vv[i])) * static_cast<double>(static_cast<TV>(s));
+        for (int j = 0; j < BS; ++j) sv += ld<double>(val + static_cast<size_t>(kd) * BS * BS + i * BS + j) * vv[j];
+      const TV st_ = static_cast<TV>(sv);
+      Dv[static_cast<size_t>(r) * BS + i] = st_;
+      acc += vv[i] * static_cast<double>(st_);
     }
   }
   const double t = block_sum_256(acc, lds);
@@ -220,16 +241,15 @@ __global__ __launch_bounds__(256) void lanczos_orth_kernel(int nbr, const double
                                                            TV* __restrict__ wy, const TV* __restrict__ dinv,
                                                            TV* __restrict__ wu, double* __restrict__ partial) {
   __shared__ double lds[4];
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   double acc = 0.0;
-  if (r < nbr) {
-    const double al = *alpha_p;
+  const double al = *alpha_p;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nbr; r += gridDim.x * blockDim.x) {
     double w[BS];
     for (int j = 0; j < BS; ++j) {
       const size_t o = static_cast<size_t>(r) * BS + j;
-      w[j] = static_cast<double>(wy[o]) - al * static_cast<double>(y[o]);
-      wy[o] = static_cast<TV>(w[j]);
-      w[j] = static_cast<double>(static_cast<TV>(w[j]));
+      const TV wt = static_cast<TV>(static_cast<double>(wy[o]) - al * static_cast<double>(y[o]));
+      wy[o] = wt;
+      w[j] = static_cast<double>(wt);
     }
     const TV* D = dinv + static_cast<size_t>(r) * BS * BS;
     for (int i = 0; i < BS; ++i) {
@@ -247,14 +267,14 @@ __global__ __launch_bounds__(256) void lanczos_orth_kernel(int nbr, const double
 // SpMV epilogue for Lanczos: wy = A u - beta_prev * y_prev ; partial u.wy
 template <class TV, class TA>
 struct EpiLanczos {
+  static constexpr bool kReduce = true;
   const TV* u;
   const TV* y_prev;
   const double* beta_prev;  // NULL on the first step
   TV* wy;
   double* partial;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ void apply(bool active, int lb, int row, int lane, const TA (&s)[BR * NR]) const {
-    __shared__ double lds[4];
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR]) const {
     double acc = 0.0;
     if (active) {
       const double bp = beta_prev ? *beta_prev : 0.0;
@@ -270,8 +290,7 @@ struct EpiLanczos {
         acc += static_cast<double>(u[o]) * static_cast<double>(wt);
       }
     }
-    const double t = block_sum_256(acc, lds);
-    if (threadIdx.x == 0) partial[lb] = t;
+    return acc;
   }
 };
 
@@ -334,6 +353,7 @@ enum SmoothMode { M_RESID = 0, M_INITX = 1, M_STEP = 2 };
 
 template <int MODE, class TV, class TA>
 struct EpiSmooth {
+  static constexpr bool kReduce = false;
   const TV* f;
   TV* r_out;
   const TV* d_in;
@@ -343,9 +363,10 @@ struct EpiSmooth {
   const TV* dinv;
   const double* coef;
   int step;
+  double* partial = nullptr;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ void apply(bool active, int, int row, int lane, const TA (&s)[BR * NR]) const {
-    if (!active) return;
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR]) const {
+    if (!active) return 0.0;
     const size_t base = static_cast<size_t>(row) * (BR * NR);
     TA r[BR * NR];
 #pragma unroll
@@ -354,7 +375,7 @@ struct EpiSmooth {
 #pragma unroll
       for (int l = 0; l < BR * NR; ++l)
         if ((l % G) == lane) r_out[base + l] = static_cast<TV>(r[l]);
-      return;
+      return 0.0;
     }
     TA z[BR * NR];
     const TV* D = dinv + static_cast<size_t>(row) * (BR * BR);
@@ -386,17 +407,18 @@ struct EpiSmooth {
       if (r_out) r_out[o] = static_cast<TV>(r[l]);
       if (d_out) d_out[o] = static_cast<TV>(dn);
     }
+    return 0.0;
   }
 };
 
 // PCG: w = A p, partial p.w
 struct EpiPcgW {
+  static constexpr bool kReduce = true;
   const double* p;
   double* w;
   double* partial;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ void apply(bool active, int lb, int row, int lane, const double (&s)[BR * NR]) const {
-    __shared__ double lds[4];
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const double (&s)[BR * NR]) const {
     double acc = 0.0;
     if (active) {
 #pragma unroll
@@ -407,8 +429,7 @@ struct EpiPcgW {
         acc += p[o] * s[l];
       }
     }
-    const double t = block_sum_256(acc, lds);
-    if (threadIdx.x == 0) partial[lb] = t;
+    return acc;
   }
 };
 
@@ -418,14 +439,14 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(size_t n, const double*
                                                          double* __restrict__ x, double* __restrict__ r,
                                                          double* __restrict__ partial) {
   __shared__ double lds[4];
-  const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
   double acc = 0.0;
-  if (g < n) {
-    const double a = sc[S_ALPHA];
+  const double a = sc[S_ALPHA];
+  for (size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; g < n;
+       g += static_cast<size_t>(gridDim.x) * blockDim.x) {
     x[g] = fmadd(a, p[g], x[g]);
     const double rv = fmadd(-a, w[g], r[g]);
     r[g] = rv;
-    acc = rv * rv;
+    acc = fmadd(rv, rv, acc);
   }
   const double t = block_sum_256(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -435,8 +456,10 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(size_t n, const double*
 __global__ __launch_bounds__(256) void dot_kernel(size_t n, const double* __restrict__ a, const double* __restrict__ b,
                                                   double* __restrict__ partial) {
   __shared__ double lds[4];
-  const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
-  const double acc = g < n ? a[g] * b[g] : 0.0;
+  double acc = 0.0;
+  for (size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; g < n;
+       g += static_cast<size_t>(gridDim.x) * blockDim.x)
+    acc = fmadd(a[g], b[g], acc);
   const double t = block_sum_256(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
@@ -453,13 +476,13 @@ __global__ void pcg_p_kernel(size_t n, const double* __restrict__ sc, int use_be
 __global__ __launch_bounds__(256) void pcg_init_kernel(size_t n, const double* __restrict__ b, double* __restrict__ x,
                                                        double* __restrict__ r, double* __restrict__ partial) {
   __shared__ double lds[4];
-  const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
   double acc = 0.0;
-  if (g < n) {
+  for (size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; g < n;
+       g += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const double v = b[g];
     r[g] = v;
     x[g] = 0.0;
-    acc = v * v;
+    acc = fmadd(v, v, acc);
   }
   const double t = block_sum_256(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -528,53 +551,150 @@ __global__ void expand_dense_kernel(int nbr, int bs, const int32_t* __restrict__
   }
 }
 
-// In-place lower Cholesky of the n x n row-major matrix M (single workgroup,
-// right-looking).  flag <- 1 on a non-positive pivot.
-__global__ __launch_bounds__(1024) void cholesky_kernel(double* __restrict__ M, int n, int* flag) {
-  const int tid = threadIdx.x;
-  const int tx = tid & 31, ty = tid >> 5;
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      double d = M[static_cast<size_t>(k) * n + k];
-      if (!(d > 0.0)) { *flag = 1; d = 1.0; }
-      M[static_cast<size_t>(k) * n + k] = sqrt(d);
-    }
-    __syncthreads();
-    const double piv = M[static_cast<size_t>(k) * n + k];
-    for (int i = k + 1 + tid; i < n; i += 1024) M[static_cast<size_t>(i) * n + k] /= piv;
-    __syncthreads();
-    for (int i = k + 1 + ty; i < n; i += 32) {
-      const double lik = M[static_cast<size_t>(i) * n + k];
-      for (int j = k + 1 + tx; j <= i; j += 32) M[static_cast<size_t>(i) * n + j] -= lik * M[static_cast<size_t>(j) * n + k];
-    }
-    __syncthreads();
+// Blocked dense Cholesky and inverse of the factor (coarsest level, FP64).
+// Tiles of kT x kT; the matrix is n x n row-major; tiles that stick out of the
+// matrix are padded with the identity on the diagonal and zeros elsewhere.
+constexpr int kT = 32;
+
+__device__ __forceinline__ double mat_at(const double* M, int n, int i, int j) {
+  if (i < n && j < n) return M[static_cast<size_t>(i) * n + j];
+  return (i == j) ? 1.0 : 0.0;
+}
+
+// Factor the diagonal tile of panel k in LDS (all threads of the block take part).
+__device__ void factor_diag_tile(const double* M, int n, int k, double (*D)[kT + 1], int* flag) {
+  const int base = k * kT;
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    D[i][j] = mat_at(M, n, base + i, base + j);
   }
-  // zero the strict upper triangle
-  for (size_t e = tid; e < static_cast<size_t>(n) * n; e += 1024) {
-    const int i = static_cast<int>(e / n), j = static_cast<int>(e % n);
-    if (j > i) M[e] = 0.0;
+  __syncthreads();
+  for (int c = 0; c < kT; ++c) {
+    if (threadIdx.x == 0) {
+      double d = D[c][c];
+      if (!(d > 0.0)) { *flag = 1; d = 1.0; }
+      D[c][c] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = D[c][c];
+    for (int i = c + 1 + threadIdx.x; i < kT; i += blockDim.x) D[i][c] /= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+      const int i = e / kT, j = e % kT;
+      if (j > c && i >= j) D[i][j] -= D[i][c] * D[j][c];
+    }
+    __syncthreads();
   }
 }
 
-// Y = L^-1 (lower), by right-looking substitution on the identity (single workgroup)
-__global__ __launch_bounds__(1024) void tri_inverse_kernel(const double* __restrict__ L, double* __restrict__ Y, int n) {
-  const int tid = threadIdx.x;
-  for (size_t e = tid; e < static_cast<size_t>(n) * n; e += 1024) {
-    const int i = static_cast<int>(e / n), j = static_cast<int>(e % n);
-    Y[e] = (i == j) ? 1.0 : 0.0;
+// Panel k: block 0 writes L_kk; block b > 0 writes L_{k+b,k} = A_{k+b,k} L_kk^-T.
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ M, int n, int k, int* flag) {
+  __shared__ double D[kT][kT + 1];
+  __shared__ double X[kT][kT + 1];
+  factor_diag_tile(M, n, k, D, flag);
+  const int I = k + static_cast<int>(blockIdx.x);
+  const int rb = I * kT, cb = k * kT;
+  if (blockIdx.x == 0) {
+    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+      const int i = e / kT, j = e % kT;
+      if (rb + i < n && cb + j < n) M[static_cast<size_t>(rb + i) * n + cb + j] = (j <= i) ? D[i][j] : 0.0;
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    X[i][j] = mat_at(M, n, rb + i, cb + j);
   }
   __syncthreads();
-  const int tx = tid & 31, ty = tid >> 5;
-  for (int k = 0; k < n; ++k) {
-    const double inv = 1.0 / L[static_cast<size_t>(k) * n + k];
-    for (int c = tid; c <= k; c += 1024) Y[static_cast<size_t>(k) * n + c] *= inv;
-    __syncthreads();
-    for (int i = k + 1 + ty; i < n; i += 32) {
-      const double lik = L[static_cast<size_t>(i) * n + k];
-      if (lik == 0.0) continue;
-      for (int c = tx; c <= k; c += 32) Y[static_cast<size_t>(i) * n + c] -= lik * Y[static_cast<size_t>(k) * n + c];
+  // row r of X: x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj
+  if (threadIdx.x < kT) {
+    const int r = threadIdx.x;
+    for (int j = 0; j < kT; ++j) {
+      double v = X[r][j];
+      for (int m = 0; m < j; ++m) v -= X[r][m] * D[j][m];
+      X[r][j] = v / D[j][j];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    if (rb + i < n && cb + j < n) M[static_cast<size_t>(rb + i) * n + cb + j] = X[i][j];
+  }
+}
+
+// Trailing update after panel k: A_IJ -= L_Ik L_Jk^T for k < J <= I (lower tiles),
+// one block per tile; tile index t enumerates the lower triangle of the trailing part.
+__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ M, int n, int k, int nt) {
+  __shared__ double Li[kT][kT + 1];
+  __shared__ double Lj[kT][kT + 1];
+  const int m = nt - k - 1;
+  int t = blockIdx.x, I = 0;
+  while (t >= I + 1) { t -= I + 1; ++I; }  // t-th tile of row I in the lower triangle
+  (void)m;
+  const int J = t;
+  const int ri = (k + 1 + I) * kT, rj = (k + 1 + J) * kT, cb = k * kT;
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    Li[i][j] = (ri + i < n && cb + j < n) ? M[static_cast<size_t>(ri + i) * n + cb + j] : 0.0;
+    Lj[i][j] = (rj + i < n && cb + j < n) ? M[static_cast<size_t>(rj + i) * n + cb + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    if (ri + i >= n || rj + j >= n) continue;
+    double sdot = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kT; ++q) sdot += Li[i][q] * Lj[j][q];
+    M[static_cast<size_t>(ri + i) * n + rj + j] -= sdot;
+  }
+}
+
+// Inverse of the lower factor, block row I: Y_IJ = L_II^-1 (delta_IJ - sum_{K=J}^{I-1} L_IK Y_KJ),
+// one block per J <= I.
+__global__ __launch_bounds__(256) void tri_inverse_row_kernel(const double* __restrict__ L, double* __restrict__ Y,
+                                                              int n, int I) {
+  __shared__ double Dd[kT][kT + 1];
+  __shared__ double S[kT][kT + 1];
+  __shared__ double A[kT][kT + 1];
+  __shared__ double Bt[kT][kT + 1];
+  const int J = blockIdx.x;
+  const int ri = I * kT, cj = J * kT;
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    Dd[i][j] = mat_at(L, n, ri + i, ri + j);
+    S[i][j] = (I == J && i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int K = J; K < I; ++K) {
+    const int rk = K * kT;
+    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+      const int i = e / kT, j = e % kT;
+      A[i][j] = (ri + i < n && rk + j < n) ? L[static_cast<size_t>(ri + i) * n + rk + j] : 0.0;
+      Bt[i][j] = (rk + i < n && cj + j < n) ? Y[static_cast<size_t>(rk + i) * n + cj + j] : 0.0;
     }
     __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+      const int i = e / kT, j = e % kT;
+      double sdot = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < kT; ++q) sdot += A[i][q] * Bt[q][j];
+      S[i][j] -= sdot;
+    }
+    __syncthreads();
+  }
+  // forward substitution L_II y = s, column j by thread j
+  if (threadIdx.x < kT) {
+    const int j = threadIdx.x;
+    for (int i = 0; i < kT; ++i) {
+      double v = S[i][j];
+      for (int q = 0; q < i; ++q) v -= Dd[i][q] * S[q][j];
+      S[i][j] = v / Dd[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int i = e / kT, j = e % kT;
+    if (ri + i < n && cj + j < n) Y[static_cast<size_t>(ri + i) * n + cj + j] = S[i][j];
   }
 }
 
@@ -607,6 +727,8 @@ __global__ void cast_vec_kernel(size_t n, const TI* __restrict__ a, TO* __restri
 }
 
 inline int vgrid(size_t n) { return static_cast<int>((n + 255) / 256); }
+// grid of a reducing grid-stride kernel: at most 2048 workgroups (= partial sums)
+inline int rgrid(size_t n) { return static_cast<int>(std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 2048))); }
 
 // ---------------------------------------------------------------------------
 // Host-side drivers
@@ -689,7 +811,7 @@ void lanczos_typed(amg_s* M, int l, hipStream_t s) {
   // roles: u_prev, u, wu, y_prev, y, wy
   int iu_prev = 0, iu = 1, iwu = 2, iy_prev = 3, iy = 4, iwy = 5;
   LevelScalars* sc = M->sc.p + l;
-  const int rg = vgrid(nbr);
+  const int rg = rgrid(nbr);
   // start: v -> (u, y) = (v, Dv) / sqrt(v.Dv)
   if (bs == 3)
     lanczos_start_kernel<3, TV, TV><<<rg, 256, 0, s>>>(nbr, M->o.lanczos_seed + static_cast<uint64_t>(l),
@@ -705,14 +827,13 @@ void lanczos_typed(amg_s* M, int l, hipStream_t s) {
   HIP_CHECK(hipGetLastError());
   const int k = M->o.lanczos_steps;
   const int G = lanes_for(A);
-  const int sg = grid_for(G, nbr);
   const TV* dinv = reinterpret_cast<const TV*>(L.dinv.p);
   for (int step = 0; step < k; ++step) {
     EpiLanczos<TV, TV> epi{V[iu], V[iy_prev], step > 0 ? sc->beta + (step - 1) : nullptr, V[iwy], M->partial.p};
-    if (bs == 3)
-      launch_rows<3, 3, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, static_cast<const TV*>(A->val), V[iu], epi, s);
-    else
-      launch_rows<6, 6, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, static_cast<const TV*>(A->val), V[iu], epi, s);
+    const int sg =
+        bs == 3
+            ? launch_rows<3, 3, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, static_cast<const TV*>(A->val), V[iu], epi, s)
+            : launch_rows<6, 6, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, static_cast<const TV*>(A->val), V[iu], epi, s);
     reduce(M, sg, sc->alpha + step, R_STORE, s);
     if (step == k - 1) break;
     if (bs == 3)
@@ -763,9 +884,15 @@ void coarse_factor(amg_s* M, hipStream_t s) {
     expand_dense_kernel<float><<<A->nbr, 64, 0, s>>>(A->nbr, A->br, A->rowptr, A->colidx,
                                                      static_cast<const float*>(A->val), M->cmat.p, n);
   HIP_CHECK(hipGetLastError());
-  cholesky_kernel<<<1, 1024, 0, s>>>(M->cmat.p, n, M->flags.p);
+  const int nt = (n + kT - 1) / kT;
+  HIP_CHECK(hipMemsetAsync(M->cY.p, 0, static_cast<size_t>(n) * n * sizeof(double), s));
+  for (int k = 0; k < nt; ++k) {
+    chol_panel_kernel<<<nt - k, 256, 0, s>>>(M->cmat.p, n, k, M->flags.p);
+    const int m = nt - k - 1;
+    if (m > 0) chol_update_kernel<<<m * (m + 1) / 2, 256, 0, s>>>(M->cmat.p, n, k, nt);
+  }
   HIP_CHECK(hipGetLastError());
-  tri_inverse_kernel<<<1, 1024, 0, s>>>(M->cmat.p, M->cY.p, n);
+  for (int I = 0; I < nt; ++I) tri_inverse_row_kernel<<<I + 1, 256, 0, s>>>(M->cmat.p, M->cY.p, n, I);
   HIP_CHECK(hipGetLastError());
   transpose_dense_kernel<<<vgrid(static_cast<size_t>(n) * n), 256, 0, s>>>(M->cY.p, M->cYt.p, n);
   HIP_CHECK(hipGetLastError());
@@ -987,6 +1114,7 @@ int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, cons
   HIP_CHECK(hipMemset(M->sc.p, 0, static_cast<size_t>(o.max_levels) * sizeof(LevelScalars)));
   // one partial per block of any reduction launch: at most nbr/4 (4 rows per block)
   M->partial.alloc(static_cast<size_t>(A0->nbr) / 4 + 8192);
+  M->partial2.alloc(256);
   M->pcg_s.alloc(S_COUNT);
   HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&M->host_s), S_COUNT * sizeof(double)));
 
@@ -1192,7 +1320,7 @@ int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol, int
   double* p = M->pp.p;
   double* w = M->pw.p;
   double* sc = M->pcg_s.p;
-  const int vg = vgrid(n);
+  const int vg = rgrid(n);
   HIP_CHECK(hipMemsetAsync(sc, 0, S_COUNT * sizeof(double), s));
   pcg_init_kernel<<<vg, 256, 0, s>>>(n, d_b, d_x, r, M->partial.p);
   HIP_CHECK(hipGetLastError());
@@ -1209,19 +1337,16 @@ int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol, int
   dot_kernel<<<vg, 256, 0, s>>>(n, r, z, M->partial.p);
   HIP_CHECK(hipGetLastError());
   reduce(M, vg, sc + S_RZ, R_STORE, s);
-  pcg_p_kernel<<<vg, 256, 0, s>>>(n, sc, 0, z, p);
+  pcg_p_kernel<<<vgrid(n), 256, 0, s>>>(n, sc, 0, z, p);
   HIP_CHECK(hipGetLastError());
   const int G = lanes_for(A);
-  const int sg = grid_for(G, A->nbr);
   bool converged = false;
   while (it < maxit) {
     EpiPcgW epi{p, w, M->partial.p};
-    if (A->br == 3)
-      launch_rows<3, 3, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx, static_cast<const double*>(A->val), p,
-                                                   epi, s);
-    else
-      launch_rows<6, 6, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx, static_cast<const double*>(A->val), p,
-                                                   epi, s);
+    const int sg = A->br == 3 ? launch_rows<3, 3, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
+                                                                            static_cast<const double*>(A->val), p, epi, s)
+                              : launch_rows<6, 6, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
+                                                                            static_cast<const double*>(A->val), p, epi, s);
     reduce(M, sg, nullptr, R_ALPHA, s);
     pcg_update_kernel<<<vg, 256, 0, s>>>(n, sc, p, w, d_x, r, M->partial.p);
     HIP_CHECK(hipGetLastError());
@@ -1239,7 +1364,7 @@ int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol, int
     dot_kernel<<<vg, 256, 0, s>>>(n, r, z, M->partial.p);
     HIP_CHECK(hipGetLastError());
     reduce(M, vg, nullptr, R_BETA, s);
-    pcg_p_kernel<<<vg, 256, 0, s>>>(n, sc, 1, z, p);
+    pcg_p_kernel<<<vgrid(n), 256, 0, s>>>(n, sc, 1, z, p);
     HIP_CHECK(hipGetLastError());
   }
   if (iters) *iters = it;

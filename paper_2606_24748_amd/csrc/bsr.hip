@@ -14,6 +14,20 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    int v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
 std::unique_ptr<bsr_s> make_owned(int32_t nbr, int32_t nbc, int32_t br, int32_t bc, int dtype,
                                   std::vector<int32_t> h_rowptr, std::vector<int32_t> h_colidx) {
   auto A = std::make_unique<bsr_s>();

@@ -11,6 +11,8 @@
 // product instead of making extra passes over HBM.
 #pragma once
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace blk {
@@ -58,14 +60,19 @@ __device__ __forceinline__ void row_product(const int32_t* __restrict__ rowptr,
   for (int t = 0; t < BR * NR; ++t) acc[t] = group_sum<G>(acc[t]);
 }
 
-// Generic kernel: every thread calls the epilogue (it may hold block-wide reductions).
+// Generic kernel: one tile of kBlock / G block rows per workgroup; logical
+// workgroups are XCD-contiguous (the hardware hands workgroup b to XCD b mod 8 and
+// each XCD has its own L2), so neighbouring rows, which gather the same x entries,
+// run on the same XCD at the same time.  A reducing epilogue (dot products) leaves
+// one partial sum per workgroup; every thread reaches that block reduction.
 template <int BR, int BC, int NR, int G, class TM, class TX, class TA, class Epi>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
                                                       const TM* __restrict__ val,
                                                       const TX* __restrict__ x, Epi epi) {
+  constexpr int kRows = kBlock / G;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
+  const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
   const int lane = static_cast<int>(threadIdx.x) % G;
   TA acc[BR * NR];
   const bool active = row < nbr;
@@ -73,34 +80,40 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
     row_product<BR, BC, NR, G, TM, TX, TA>(rowptr, colidx, val, x, row, lane, acc);
   } else {
 #pragma unroll
-    for (int t = 0; t < BR * NR; ++t) acc[t] = TA(0);
+    for (int z = 0; z < BR * NR; ++z) acc[z] = TA(0);
   }
-  epi.template apply<BR, NR, G>(active, lb, row, lane, acc);
+  const double part = epi.template apply<BR, NR, G>(active, row, lane, acc);
+  if constexpr (Epi::kReduce) {
+    __shared__ double lds[4];
+    const double sum = block_sum_256(part, lds);
+    if (threadIdx.x == 0) epi.partial[lb] = sum;
+  }
 }
 
-template <int G>
-inline int grid_for_rows(int nbr) { return ceil_div(nbr, kBlock / G); }
 
-// Launch spmv_kernel with G chosen at run time from {8, 16, 32, 64}.
+template <int BR, int BC, int NR, int G, class TM, class TX, class TA, class Epi>
+int launch_g(int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val, const TX* x, const Epi& epi,
+             hipStream_t s) {
+  const int grid = ceil_div(nbr, kBlock / G);
+  spmv_kernel<BR, BC, NR, G, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+  return grid;
+}
+
+// Launch spmv_kernel with G chosen at run time from {8, 16, 32, 64}; returns the
+// number of workgroups (= number of partial sums written by a reducing epilogue).
 template <int BR, int BC, int NR, class TM, class TX, class TA, class Epi>
-void launch_rows(int G, int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val,
-                 const TX* x, const Epi& epi, hipStream_t s) {
-  if (nbr <= 0) return;
+int launch_rows(int G, int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val, const TX* x,
+                const Epi& epi, hipStream_t s) {
+  if (nbr <= 0) return 0;
+  int grid;
   switch (G) {
-    case 8:
-      spmv_kernel<BR, BC, NR, 8, TM, TX, TA, Epi><<<grid_for_rows<8>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
-      break;
-    case 16:
-      spmv_kernel<BR, BC, NR, 16, TM, TX, TA, Epi><<<grid_for_rows<16>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
-      break;
-    case 32:
-      spmv_kernel<BR, BC, NR, 32, TM, TX, TA, Epi><<<grid_for_rows<32>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
-      break;
-    default:
-      spmv_kernel<BR, BC, NR, 64, TM, TX, TA, Epi><<<grid_for_rows<64>(nbr), kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
-      break;
+    case 8: grid = launch_g<BR, BC, NR, 8, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s); break;
+    case 16: grid = launch_g<BR, BC, NR, 16, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s); break;
+    case 32: grid = launch_g<BR, BC, NR, 32, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s); break;
+    default: grid = launch_g<BR, BC, NR, 64, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s); break;
   }
   HIP_CHECK(hipGetLastError());
+  return grid;
 }
 
 inline int grid_for(int G, int nbr) { return ceil_div(nbr, kBlock / G); }
@@ -108,17 +121,20 @@ inline int grid_for(int G, int nbr) { return ceil_div(nbr, kBlock / G); }
 // y = alpha * (A x) + beta * y
 template <class TY, class TA>
 struct EpiAxpby {
+  static constexpr bool kReduce = false;
   TY* __restrict__ y;
   TA alpha, beta;
+  double* partial = nullptr;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ void apply(bool active, int, int row, int lane, const TA (&acc)[BR * NR]) const {
-    if (!active) return;
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&acc)[BR * NR]) const {
+    if (!active) return 0.0;
     for (int l = lane; l < BR * NR; l += G) {
       const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
       TA v = alpha * pick(acc, l);
       if (beta != TA(0)) v = fmadd(beta, ld<TA>(y + o), v);
       st(y + o, v);
     }
+    return 0.0;
   }
 };
 
