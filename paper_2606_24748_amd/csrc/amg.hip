@@ -274,7 +274,24 @@ struct EpiLanczos {
   TV* wy;
   double* partial;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR]) const {
+  __device__ __forceinline__ RowVals<double, 2 * BR * NR> prefetch(bool active, int row) const {
+    RowVals<double, 2 * BR * NR> p;
+#pragma unroll
+    for (int t = 0; t < 2 * BR * NR; ++t) p.v[t] = 0.0;
+    if (active) {
+      const size_t b = static_cast<size_t>(row) * (BR * NR);
+#pragma unroll
+      for (int t = 0; t < BR * NR; ++t) {
+        p.v[t] = static_cast<double>(u[b + t]);
+        // y_prev is not read on the first step (its buffer holds no data yet)
+        if (beta_prev) p.v[BR * NR + t] = static_cast<double>(y_prev[b + t]);
+      }
+    }
+    return p;
+  }
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR],
+                                          const RowVals<double, 2 * BR * NR>& pre) const {
     double acc = 0.0;
     if (active) {
       const double bp = beta_prev ? *beta_prev : 0.0;
@@ -282,12 +299,10 @@ struct EpiLanczos {
       for (int l = 0; l < BR * NR; ++l) {
         if ((l % G) != lane) continue;
         const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
-        // y_prev is not read on the first step (its buffer holds no data yet)
-        const double w = beta_prev ? static_cast<double>(s[l]) - bp * static_cast<double>(y_prev[o])
-                                   : static_cast<double>(s[l]);
+        const double w = static_cast<double>(s[l]) - bp * pre.v[BR * NR + l];
         const TV wt = static_cast<TV>(w);
         wy[o] = wt;
-        acc += static_cast<double>(u[o]) * static_cast<double>(wt);
+        acc += pre.v[l] * static_cast<double>(wt);
       }
     }
     return acc;
@@ -364,28 +379,53 @@ struct EpiSmooth {
   const double* coef;
   int step;
   double* partial = nullptr;
+  // own-row operands: f (BR*NR), d_in (BR*NR), x_in (BR*NR), Dinv (BR*BR)
   template <int BR, int NR, int G>
-  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR]) const {
-    if (!active) return 0.0;
-    const size_t base = static_cast<size_t>(row) * (BR * NR);
-    TA r[BR * NR];
+  __device__ __forceinline__ RowVals<TA, 3 * BR * NR + BR * BR> prefetch(bool active, int row) const {
+    constexpr int N = BR * NR;
+    RowVals<TA, 3 * N + BR * BR> p;
 #pragma unroll
-    for (int t = 0; t < BR * NR; ++t) r[t] = ld<TA>(f + base + t) - s[t];
+    for (int t = 0; t < 3 * N + BR * BR; ++t) p.v[t] = TA(0);
+    if (!active) return p;
+    const size_t b = static_cast<size_t>(row) * N;
+#pragma unroll
+    for (int t = 0; t < N; ++t) p.v[t] = ld<TA>(f + b + t);
+    if (MODE == M_STEP) {
+#pragma unroll
+      for (int t = 0; t < N; ++t) p.v[N + t] = ld<TA>(d_in + b + t);
+    }
+    if (MODE != M_RESID) {
+#pragma unroll
+      for (int t = 0; t < N; ++t) p.v[2 * N + t] = ld<TA>(x_in + b + t);
+      const TV* D = dinv + static_cast<size_t>(row) * (BR * BR);
+#pragma unroll
+      for (int t = 0; t < BR * BR; ++t) p.v[3 * N + t] = ld<TA>(D + t);
+    }
+    return p;
+  }
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR],
+                                          const RowVals<TA, 3 * BR * NR + BR * BR>& pre) const {
+    constexpr int N = BR * NR;
+    if (!active) return 0.0;
+    const size_t base = static_cast<size_t>(row) * N;
+    TA r[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) r[t] = pre.v[t] - s[t];
     if (MODE == M_RESID) {
 #pragma unroll
-      for (int l = 0; l < BR * NR; ++l)
+      for (int l = 0; l < N; ++l)
         if ((l % G) == lane) r_out[base + l] = static_cast<TV>(r[l]);
       return 0.0;
     }
-    TA z[BR * NR];
-    const TV* D = dinv + static_cast<size_t>(row) * (BR * BR);
+    TA z[N];
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
 #pragma unroll
       for (int q = 0; q < NR; ++q) z[i * NR + q] = TA(0);
 #pragma unroll
       for (int j = 0; j < BR; ++j) {
-        const TA dij = ld<TA>(D + i * BR + j);
+        const TA dij = pre.v[3 * N + i * BR + j];
 #pragma unroll
         for (int q = 0; q < NR; ++q) z[i * NR + q] = fmadd(dij, r[j * NR + q], z[i * NR + q]);
       }
@@ -398,12 +438,12 @@ struct EpiSmooth {
       c2 = static_cast<TA>(coef[2 + 2 * step]);
     }
 #pragma unroll
-    for (int l = 0; l < BR * NR; ++l) {
+    for (int l = 0; l < N; ++l) {
       if ((l % G) != lane) continue;
       const size_t o = base + l;
       TA dn = c2 * z[l];
-      if (MODE == M_STEP) dn = fmadd(c1, ld<TA>(d_in + o), dn);
-      x_out[o] = static_cast<TV>(ld<TA>(x_in + o) + dn);
+      if (MODE == M_STEP) dn = fmadd(c1, pre.v[N + l], dn);
+      x_out[o] = static_cast<TV>(pre.v[2 * N + l] + dn);
       if (r_out) r_out[o] = static_cast<TV>(r[l]);
       if (d_out) d_out[o] = static_cast<TV>(dn);
     }
@@ -418,7 +458,15 @@ struct EpiPcgW {
   double* w;
   double* partial;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ double apply(bool active, int row, int lane, const double (&s)[BR * NR]) const {
+  __device__ __forceinline__ RowVals<double, BR * NR> prefetch(bool active, int row) const {
+    RowVals<double, BR * NR> pv;
+#pragma unroll
+    for (int t = 0; t < BR * NR; ++t) pv.v[t] = active ? p[static_cast<size_t>(row) * (BR * NR) + t] : 0.0;
+    return pv;
+  }
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ double apply(bool active, int row, int lane, const double (&s)[BR * NR],
+                                          const RowVals<double, BR * NR>& pre) const {
     double acc = 0.0;
     if (active) {
 #pragma unroll
@@ -426,7 +474,7 @@ struct EpiPcgW {
         if ((l % G) != lane) continue;
         const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
         w[o] = s[l];
-        acc += p[o] * s[l];
+        acc += pre.v[l] * s[l];
       }
     }
     return acc;

@@ -1,5 +1,6 @@
 // Rectangular-block sparse matrix handle, SpMV and SpMV-transpose (paper §2.3, §4.2),
 // and the C-ABI error plumbing.
+#include <cstdio>
 #include <cstdlib>
 
 #include "spmv_core.hpp"
@@ -57,12 +58,28 @@ void ensure_host_pattern(bsr_s* A) {
   A->h_pattern = true;
 }
 
+// (G, U) for a matrix: G lanes per block row, U blocks per lane per step.  The
+// heuristic targets about one step per row with enough bytes in flight per wave;
+// BLKAMG_SPMV_LANES="GxU" overrides it (experiments).
 int lanes_for(const bsr_s* A) {
+  static int forced = -1;
+  if (forced < 0) {
+    forced = 0;
+    if (const char* e = std::getenv("BLKAMG_SPMV_LANES")) {
+      int g = 0, u = 0;
+      if (std::sscanf(e, "%dx%d", &g, &u) == 2) forced = g * 8 + u;
+    }
+  }
+  if (forced > 0) return forced;
   const double avg = A->avg_blocks_per_row();
-  if (avg <= 8.0) return 8;
-  if (avg <= 16.0) return 16;
-  if (avg <= 40.0) return 32;
-  return 64;
+  const size_t vb = A->block_elems() * dtype_size(A->dtype);  // bytes per block
+  int G;
+  if (avg <= 8.0) G = 8;
+  else if (avg <= 16.0) G = 16;
+  else if (avg <= 40.0) G = 32;
+  else G = 64;
+  (void)vb;  // measured at 128^3: one block per lane beats two for both F32 and F64
+  return G * 8 + 1;
 }
 
 namespace {

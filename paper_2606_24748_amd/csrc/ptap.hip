@@ -6,10 +6,25 @@
 // The transpose R comes from P's value-stamped cache, so a recompute with an
 // unchanged prolongator never rebuilds prolongator-side data (paper §3.5).
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <string>
+#include <type_traits>
 
 #include "spmv_core.hpp"
 
 namespace blk {
+
+// Contributions to one output block, listed once at symbolic time: each entry packs
+// (index within the first operand's row, index within the second operand's row)
+// into `width` bytes, high part shifted left by `shift`.
+struct PairList {
+  DevBuf<uint8_t> codes;
+  DevBuf<int32_t> ptr;  // ptr[s]..ptr[s+1]: entries of output block s
+  int width = 0;        // 1, 2 or 4 bytes; 0 = not built (use the searching kernels)
+  int shift = 0;
+};
 
 struct PtapPlan {
   const bsr_s* A = nullptr;
@@ -19,6 +34,12 @@ struct PtapPlan {
   DevBuf<int32_t> ap_rowptr, ap_colidx;
   DevBuf<char> ap_val;  // scratch for A P in the accumulation type
   int g_ap = 32, g_c = 32;
+  PairList ap_pairs;    // per AP block: (block of A row i, block of P row j)
+  PairList c_pairs;     // per C block: (entry of R row a, block of AP row i)
+  int64_t ap_nslots = 0;
+  DevBuf<int32_t> ap_slot_row0, c_slot_row0;  // row of the first block of each workgroup
+  DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
+  bool ap_vec = true, c_vec = true;
 };
 
 namespace {
@@ -123,25 +144,369 @@ __global__ __launch_bounds__(kBlock) void rap_kernel(int ncoarse, const int32_t*
   }
 }
 
+// pass 1 with pair lists: lane per AP block, no searching.
+template <int BR, int BC, int G, class TA_, class TP, class TA, class CT>
+__global__ __launch_bounds__(kBlock) void ap_pairs_kernel(int nrows, const int32_t* __restrict__ a_rp,
+                                                          const int32_t* __restrict__ a_ci, const TA_* __restrict__ a_v,
+                                                          const int32_t* __restrict__ p_rp, const TP* __restrict__ p_v,
+                                                          const int32_t* __restrict__ ap_rp,
+                                                          const int32_t* __restrict__ pp, const CT* __restrict__ codes,
+                                                          int shift, TA* __restrict__ ap_v) {
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
+  const int lane = static_cast<int>(threadIdx.x) % G;
+  if (row >= nrows) return;
+  const int k0 = a_rp[row];
+  const uint32_t mask = (1u << shift) - 1u;
+  for (int sidx = ap_rp[row] + lane; sidx < ap_rp[row + 1]; sidx += G) {
+    TA acc[BR * BC];
+#pragma unroll
+    for (int t = 0; t < BR * BC; ++t) acc[t] = TA(0);
+    const int e1 = pp[sidx + 1];
+    for (int e = pp[sidx]; e < e1; ++e) {
+      const uint32_t c = codes[e];
+      const int k = k0 + static_cast<int>(c >> shift);
+      const int q = p_rp[a_ci[k]] + static_cast<int>(c & mask);
+      const TA_* ab = a_v + static_cast<size_t>(k) * (BR * BR);
+      const TP* pb = p_v + static_cast<size_t>(q) * (BR * BC);
+      TA pv[BR * BC];
+#pragma unroll
+      for (int t = 0; t < BR * BC; ++t) pv[t] = ld<TA>(pb + t);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+#pragma unroll
+        for (int m = 0; m < BR; ++m) {
+          const TA av = ld<TA>(ab + r * BR + m);
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(av, pv[m * BC + cc], acc[r * BC + cc]);
+        }
+      }
+    }
+    TA* o = ap_v + static_cast<size_t>(sidx) * (BR * BC);
+#pragma unroll
+    for (int t = 0; t < BR * BC; ++t) o[t] = acc[t];
+  }
+}
+
+// pass 2 with pair lists: lane per C block.
+template <int BR, int BC, int G, class TR, class TA, class TC, class CT>
+__global__ __launch_bounds__(kBlock) void rap_pairs_kernel(int ncoarse, const int32_t* __restrict__ r_rp,
+                                                           const int32_t* __restrict__ r_ci, const TR* __restrict__ r_v,
+                                                           const int32_t* __restrict__ ap_rp, const TA* __restrict__ ap_v,
+                                                           const int32_t* __restrict__ c_rp,
+                                                           const int32_t* __restrict__ pp, const CT* __restrict__ codes,
+                                                           int shift, TC* __restrict__ c_v) {
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
+  const int lane = static_cast<int>(threadIdx.x) % G;
+  if (row >= ncoarse) return;
+  const int t0 = r_rp[row];
+  const uint32_t mask = (1u << shift) - 1u;
+  for (int sidx = c_rp[row] + lane; sidx < c_rp[row + 1]; sidx += G) {
+    TA acc[BC * BC];
+#pragma unroll
+    for (int t = 0; t < BC * BC; ++t) acc[t] = TA(0);
+    const int e1 = pp[sidx + 1];
+    for (int e = pp[sidx]; e < e1; ++e) {
+      const uint32_t c = codes[e];
+      const int t = t0 + static_cast<int>(c >> shift);
+      const int q = ap_rp[r_ci[t]] + static_cast<int>(c & mask);
+      const TR* rb = r_v + static_cast<size_t>(t) * (BC * BR);
+      const TA* apb = ap_v + static_cast<size_t>(q) * (BR * BC);
+      TA apv[BR * BC];
+#pragma unroll
+      for (int z = 0; z < BR * BC; ++z) apv[z] = apb[z];
+#pragma unroll
+      for (int r = 0; r < BC; ++r) {
+#pragma unroll
+        for (int m = 0; m < BR; ++m) {
+          const TA rv = ld<TA>(rb + r * BR + m);
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(rv, apv[m * BC + cc], acc[r * BC + cc]);
+        }
+      }
+    }
+    TC* o = c_v + static_cast<size_t>(sidx) * (BC * BC);
+#pragma unroll
+    for (int z = 0; z < BC * BC; ++z) st(o + z, acc[z]);
+  }
+}
+
+// Column-lane mapping: NC lanes per output block, lane c owns output column c
+// (BR values for AP, NC values for C), so the NC lanes of a block read each
+// contributing P / AP block as one contiguous stretch and share the A / R block.
+// A workgroup covers kSlots consecutive output blocks; slot_row0[w] is the row of its
+// first block (rows of the following blocks are found by scanning forward).
+template <int NC>
+struct ColMap {
+  static constexpr int kSlots = kBlock / NC;  // 42 for NC = 6
+};
+
+template <int BR, int NC, class TA_, class TP, class TA, class CT>
+__global__ __launch_bounds__(kBlock) void ap_cols_kernel(int64_t nslots, const int32_t* __restrict__ slot_row0,
+                                                         const int32_t* __restrict__ a_rp,
+                                                         const int32_t* __restrict__ a_ci, const TA_* __restrict__ a_v,
+                                                         const int32_t* __restrict__ p_rp, const TP* __restrict__ p_v,
+                                                         const int32_t* __restrict__ ap_rp,
+                                                         const int32_t* __restrict__ pp, const CT* __restrict__ codes,
+                                                         int shift, TA* __restrict__ ap_v) {
+  constexpr int kS = ColMap<NC>::kSlots;
+  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tid = static_cast<int>(threadIdx.x);
+  if (tid >= kS * NC) return;
+  const int64_t sidx = static_cast<int64_t>(w) * kS + tid / NC;
+  const int c = tid % NC;
+  if (sidx >= nslots) return;
+  int row = slot_row0[w];
+  while (ap_rp[row + 1] <= sidx) ++row;
+  const int k0 = a_rp[row];
+  const uint32_t mask = (1u << shift) - 1u;
+  TA acc[BR];
+#pragma unroll
+  for (int r = 0; r < BR; ++r) acc[r] = TA(0);
+  const int e1 = pp[sidx + 1];
+  for (int e = pp[sidx]; e < e1; ++e) {
+    const uint32_t code = codes[e];
+    const int k = k0 + static_cast<int>(code >> shift);
+    const int q = p_rp[a_ci[k]] + static_cast<int>(code & mask);
+    const TA_* ab = a_v + static_cast<size_t>(k) * (BR * BR);
+    const TP* pb = p_v + static_cast<size_t>(q) * (BR * NC) + c;
+    TA pc[BR];
+#pragma unroll
+    for (int m = 0; m < BR; ++m) pc[m] = ld<TA>(pb + m * NC);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+#pragma unroll
+      for (int m = 0; m < BR; ++m) acc[r] = fmadd(ld<TA>(ab + r * BR + m), pc[m], acc[r]);
+    }
+  }
+  TA* o = ap_v + static_cast<size_t>(sidx) * (BR * NC) + c;
+#pragma unroll
+  for (int r = 0; r < BR; ++r) o[r * NC] = acc[r];
+}
+
+template <int BR, int NC, class TR, class TA, class TC, class CT>
+__global__ __launch_bounds__(kBlock) void rap_cols_kernel(int64_t nslots, const int32_t* __restrict__ slot_row0,
+                                                          const int32_t* __restrict__ r_rp,
+                                                          const int32_t* __restrict__ r_ci, const TR* __restrict__ r_v,
+                                                          const int32_t* __restrict__ ap_rp, const TA* __restrict__ ap_v,
+                                                          const int32_t* __restrict__ c_rp,
+                                                          const int32_t* __restrict__ pp, const CT* __restrict__ codes,
+                                                          int shift, TC* __restrict__ c_v) {
+  constexpr int kS = ColMap<NC>::kSlots;
+  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tid = static_cast<int>(threadIdx.x);
+  if (tid >= kS * NC) return;
+  const int64_t sidx = static_cast<int64_t>(w) * kS + tid / NC;
+  const int c = tid % NC;
+  if (sidx >= nslots) return;
+  int row = slot_row0[w];
+  while (c_rp[row + 1] <= sidx) ++row;
+  const int t0 = r_rp[row];
+  const uint32_t mask = (1u << shift) - 1u;
+  TA acc[NC];
+#pragma unroll
+  for (int r = 0; r < NC; ++r) acc[r] = TA(0);
+  const int e1 = pp[sidx + 1];
+  for (int e = pp[sidx]; e < e1; ++e) {
+    const uint32_t code = codes[e];
+    const int t = t0 + static_cast<int>(code >> shift);
+    const int q = ap_rp[r_ci[t]] + static_cast<int>(code & mask);
+    const TR* rb = r_v + static_cast<size_t>(t) * (NC * BR);
+    const TA* apb = ap_v + static_cast<size_t>(q) * (BR * NC) + c;
+    TA ac[BR];
+#pragma unroll
+    for (int m = 0; m < BR; ++m) ac[m] = apb[m * NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+#pragma unroll
+      for (int m = 0; m < BR; ++m) acc[r] = fmadd(ld<TA>(rb + r * BR + m), ac[m], acc[r]);
+    }
+  }
+  TC* o = c_v + static_cast<size_t>(sidx) * (NC * NC) + c;
+#pragma unroll
+  for (int r = 0; r < NC; ++r) st(o + r * NC, acc[r]);
+}
+
+// Lane per output block.  A workgroup takes kBlock consecutive output blocks, which
+// belong to rows row0..row1 (row1 = first row of the next workgroup), and walks them
+// in the order given by `perm` (sorted by contribution count at symbolic time, so the
+// lanes of a wave run loops of similar length).  For every entry k of those rows of
+// the first operand X (A or R), LDS holds ystart[k] = the start of the Y row it
+// multiplies (P row a_ci[k], or AP row r_ci[k]); when they fit, the X blocks of the
+// rows are staged in LDS too (one coalesced copy).  Y blocks are read with 16-byte
+// (FP64) or 8-byte (FP32) vector loads when VEC is set.
+constexpr int kMaxR = 48;
+constexpr int kLdsEntries = 2048;
+constexpr int kLdsXBytes = 45056;
+
+template <class T, bool VEC, int N>
+__device__ __forceinline__ void load_y(const T* __restrict__ p, T (&v)[N]) {
+  if constexpr (VEC && sizeof(T) == 8 && N % 2 == 0) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int t = 0; t < N / 2; ++t) {
+      const double2 d = q[t];
+      v[2 * t] = d.x;
+      v[2 * t + 1] = d.y;
+    }
+  } else if constexpr (VEC && sizeof(T) == 4 && N % 2 == 0) {
+    const float2* q = reinterpret_cast<const float2*>(p);
+#pragma unroll
+    for (int t = 0; t < N / 2; ++t) {
+      const float2 d = q[t];
+      v[2 * t] = d.x;
+      v[2 * t + 1] = d.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < N; ++t) v[t] = p[t];
+  }
+}
+
+template <int BR, int BC, class TX, class TY, class TA, class CT, bool kIsAP, bool VEC>
+__global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int nrows, const int32_t* __restrict__ slot_row0,
+                                                            const uint8_t* __restrict__ perm,
+                                                            const int32_t* __restrict__ x_rp,
+                                                            const int32_t* __restrict__ x_ci, const TX* __restrict__ x_v,
+                                                            const int32_t* __restrict__ y_rp, const TY* __restrict__ y_v,
+                                                            const int32_t* __restrict__ o_rp,
+                                                            const int32_t* __restrict__ pp, const CT* __restrict__ codes,
+                                                            int shift, void* __restrict__ out) {
+  // kIsAP: X = A (BR x BR), Y = P (BR x BC), out AP (BR x BC) in TA
+  // else : X = R (BC x BR), Y = AP (BR x BC), out C (BC x BC) in the type of A
+  constexpr int XR = kIsAP ? BR : BC;  // rows of an X block
+  constexpr int XC = BR;               // cols of an X block
+  constexpr int XB = XR * XC;
+  constexpr int OR = XR;               // rows of an output block
+  // only the AP pass stages X (A rows: ~27 blocks per row); R rows are too long
+  constexpr int kXCap = kIsAP ? kLdsXBytes / (XB * static_cast<int>(sizeof(TX))) : 1;
+  __shared__ int32_t ystart[kLdsEntries];
+  __shared__ TX xs[kXCap * XB];
+  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int64_t s_begin = static_cast<int64_t>(w) * kBlock;
+  const int row0 = slot_row0[w];
+  const int row1 = min(nrows - 1, slot_row0[w + 1]);
+  const int nr = row1 - row0 + 1;
+  const int kbase = x_rp[row0];
+  const int nk = x_rp[row1 + 1] - kbase;
+  const bool staged = nr <= kMaxR && nk <= kLdsEntries;
+  const bool xstaged = kIsAP && staged && nk <= kXCap;
+  if (staged) {
+    for (int t = threadIdx.x; t < nk; t += kBlock) ystart[t] = y_rp[x_ci[kbase + t]];
+  }
+  if (xstaged) {
+    const TX* src = x_v + static_cast<size_t>(kbase) * XB;
+    for (int t = threadIdx.x; t < nk * XB; t += kBlock) xs[t] = src[t];
+  }
+  __syncthreads();
+  const int64_t lim = nslots - s_begin;
+  if (static_cast<int64_t>(threadIdx.x) >= lim) return;
+  const int64_t sidx = s_begin + perm[s_begin + threadIdx.x];
+  int row = row0;
+  while (o_rp[row + 1] <= sidx) ++row;
+  const int k0 = x_rp[row];
+  const uint32_t mask = (1u << shift) - 1u;
+  TA acc[OR * BC];
+#pragma unroll
+  for (int t = 0; t < OR * BC; ++t) acc[t] = TA(0);
+  const int e0 = pp[sidx], e1 = pp[sidx + 1];
+  for (int e = e0; e < e1; ++e) {
+    const uint32_t code = codes[e];
+    const int k = k0 + static_cast<int>(code >> shift);
+    const int ys = staged ? ystart[k - kbase] : y_rp[x_ci[k]];
+    const int q = ys + static_cast<int>(code & mask);
+    TY yraw[BR * BC];
+    load_y<TY, VEC>(y_v + static_cast<size_t>(q) * (BR * BC), yraw);
+    TA yv[BR * BC];
+#pragma unroll
+    for (int t = 0; t < BR * BC; ++t) yv[t] = ld<TA>(&yraw[t]);
+    const TX* xb = xstaged ? xs + (k - kbase) * XB : x_v + static_cast<size_t>(k) * XB;
+#pragma unroll
+    for (int r = 0; r < OR; ++r) {
+#pragma unroll
+      for (int m = 0; m < XC; ++m) {
+        const TA xv = ld<TA>(xb + r * XC + m);
+#pragma unroll
+        for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(xv, yv[m * BC + cc], acc[r * BC + cc]);
+      }
+    }
+  }
+  if constexpr (kIsAP) {
+    TA* o = static_cast<TA*>(out) + static_cast<size_t>(sidx) * (OR * BC);
+#pragma unroll
+    for (int t = 0; t < OR * BC; ++t) o[t] = acc[t];
+  } else {
+    using TC = typename std::conditional<sizeof(TA) == 8, double, float>::type;
+    TC* o = static_cast<TC*>(out) + static_cast<size_t>(sidx) * (OR * BC);
+#pragma unroll
+    for (int t = 0; t < OR * BC; ++t) st(o + t, acc[t]);
+  }
+}
+
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+template <int BR, int BC, class TA_, class TP, class TA, class CT>
+void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap, hipStream_t s) {
+  const int64_t ns = pl.ap_nslots;
+  const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
+  if (grid == 0) return;
+  // P blocks (BR*BC values) can be read with 2-element vector loads when the block
+  // size is even and the array is aligned for it
+  const bool vec = pl.ap_vec && (BR * BC) % 2 == 0 && aligned(P->val, 2 * sizeof(TP)) && sizeof(TP) >= 4;
+#define BLK_APK(V)                                                                                                   \
+  pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, 0, s>>>(                                        \
+      ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
+      static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_pairs.ptr.p,                                             \
+      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap)
+  if (vec) BLK_APK(true); else BLK_APK(false);
+#undef BLK_APK
+}
+
+template <int BR, int BC, class TA_, class TP, class TA, class CT>
+void launch_rap_pairs(const PtapPlan& pl, const bsr_s* R, const bsr_s* C, const TA* ap, hipStream_t s) {
+  const int64_t ns = C->nnzb;
+  const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
+  if (grid == 0) return;
+#define BLK_RAPK(V)                                                                                                  \
+  pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V><<<grid, kBlock, 0, s>>>(                                        \
+      ns, C->nbr, pl.c_slot_row0.p, pl.c_perm.p, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, \
+      ap, C->rowptr, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val)
+  if (pl.c_vec) BLK_RAPK(true); else BLK_RAPK(false);
+#undef BLK_RAPK
+}
+
 template <int BR, int BC, class TA_, class TP, class TA>
 void run_numeric(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, const bsr_s* R, bsr_s* C, hipStream_t s) {
   TA* ap = reinterpret_cast<TA*>(pl.ap_val.p);
   if (A->nbr > 0) {
+    switch (pl.ap_pairs.width) {
+      case 1: launch_ap_pairs<BR, BC, TA_, TP, TA, uint8_t>(pl, A, P, ap, s); break;
+      case 2: launch_ap_pairs<BR, BC, TA_, TP, TA, uint16_t>(pl, A, P, ap, s); break;
+      case 4: launch_ap_pairs<BR, BC, TA_, TP, TA, uint32_t>(pl, A, P, ap, s); break;
+      default:
 #define BLK_AP(GG)                                                                                      \
   ap_kernel<BR, BC, GG, TA_, TP, TA><<<grid_for(GG, A->nbr), kBlock, 0, s>>>(                            \
       A->nbr, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, P->colidx,               \
       static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_colidx.p, ap)
-    if (pl.g_ap == 16) BLK_AP(16); else BLK_AP(32);
+        if (pl.g_ap == 16) BLK_AP(16); else BLK_AP(32);
 #undef BLK_AP
+    }
     HIP_CHECK(hipGetLastError());
   }
   if (C->nbr > 0) {
+    switch (pl.c_pairs.width) {
+      case 1: launch_rap_pairs<BR, BC, TA_, TP, TA, uint8_t>(pl, R, C, ap, s); break;
+      case 2: launch_rap_pairs<BR, BC, TA_, TP, TA, uint16_t>(pl, R, C, ap, s); break;
+      case 4: launch_rap_pairs<BR, BC, TA_, TP, TA, uint32_t>(pl, R, C, ap, s); break;
+      default:
 #define BLK_RAP(GG)                                                                                     \
   rap_kernel<BR, BC, GG, TP, TA, TA_><<<grid_for(GG, C->nbr), kBlock, 0, s>>>(                           \
       C->nbr, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, pl.ap_colidx.p, ap,  \
       C->rowptr, C->colidx, static_cast<TA_*>(C->val))
-    if (pl.g_c == 16) BLK_RAP(16); else BLK_RAP(32);
+        if (pl.g_c == 16) BLK_RAP(16); else BLK_RAP(32);
 #undef BLK_RAP
+    }
     HIP_CHECK(hipGetLastError());
   }
 }
@@ -187,6 +552,135 @@ void structural_product_host(int32_t nra, const std::vector<int32_t>& rpa, const
   }
 }
 
+namespace {
+
+template <class F>
+void parallel_rows(int32_t n, F&& f) {
+  const int nth = std::max(1, std::min<int>(16, static_cast<int>(std::thread::hardware_concurrency())));
+  if (n < 4096 || nth == 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> ts;
+  for (int t = 0; t < nth; ++t)
+    ts.emplace_back([&, t] { f(static_cast<int32_t>(static_cast<int64_t>(n) * t / nth),
+                               static_cast<int32_t>(static_cast<int64_t>(n) * (t + 1) / nth), t); });
+  for (auto& th : ts) th.join();
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while ((int64_t{1} << b) <= v) ++b;
+  return b;
+}
+
+// Build the pair list of a product Out = X * Y on known patterns: output block
+// (row, col) collects every (k, q) with X_{row, x_ci[k]} and Y_{x_ci[k], col} stored,
+// where q indexes Y's row x_ci[k].  Codes store (k - x_rp[row], q - y_rp[x_ci[k]]).
+// Entries of one output are ordered by k then q.
+void build_pairs(int32_t nrows, int32_t ncols, const std::vector<int32_t>& x_rp, const std::vector<int32_t>& x_ci,
+                 const std::vector<int32_t>& y_rp, const std::vector<int32_t>& y_ci, const std::vector<int32_t>& o_rp,
+                 const std::vector<int32_t>& o_ci, bool allow_byte, PairList& out) {
+  const int nth = std::max(1, std::min<int>(16, static_cast<int>(std::thread::hardware_concurrency())));
+  const size_t nout = o_ci.size();
+  std::vector<int32_t> cnt(nout + 1, 0);
+  std::vector<int64_t> max_hi(nth, 0), max_lo(nth, 0);
+  std::vector<std::vector<int32_t>> pos(nth);
+  // pass 1: counts and ranges
+  parallel_rows(nrows, [&](int32_t r0, int32_t r1, int tid) {
+    auto& ps = pos[tid];
+    ps.assign(static_cast<size_t>(ncols), -1);
+    for (int32_t r = r0; r < r1; ++r) {
+      for (int32_t sidx = o_rp[r]; sidx < o_rp[r + 1]; ++sidx) ps[o_ci[sidx]] = sidx;
+      for (int32_t k = x_rp[r]; k < x_rp[r + 1]; ++k) {
+        const int32_t j = x_ci[k];
+        max_hi[tid] = std::max<int64_t>(max_hi[tid], k - x_rp[r]);
+        for (int32_t q = y_rp[j]; q < y_rp[j + 1]; ++q) {
+          cnt[ps[y_ci[q]] + 1]++;
+          max_lo[tid] = std::max<int64_t>(max_lo[tid], q - y_rp[j]);
+        }
+      }
+    }
+  });
+  int64_t mh = 0, ml = 0;
+  for (int t = 0; t < nth; ++t) { mh = std::max(mh, max_hi[t]); ml = std::max(ml, max_lo[t]); }
+  const int bh = bits_for(mh), bl = bits_for(ml);
+  int width;
+  if (allow_byte && bh + bl <= 8) width = 1;
+  else if (bh + bl <= 16) width = 2;
+  else if (bh + bl <= 32) width = 4;
+  else { out.width = 0; return; }
+  std::vector<int32_t> ptr(nout + 1, 0);
+  for (size_t sidx = 0; sidx < nout; ++sidx) {
+    BLK_REQUIRE(static_cast<int64_t>(ptr[sidx]) + cnt[sidx + 1] <= INT32_MAX, BLKAMG_EINVAL, "pair list too long");
+    ptr[sidx + 1] = ptr[sidx] + cnt[sidx + 1];
+  }
+  std::vector<uint8_t> codes(static_cast<size_t>(ptr[nout]) * width);
+  // pass 2: fill (each row writes only its own output range)
+  parallel_rows(nrows, [&](int32_t r0, int32_t r1, int tid) {
+    auto& ps = pos[tid];
+    std::vector<int32_t> cur;
+    for (int32_t r = r0; r < r1; ++r) {
+      const int32_t s0 = o_rp[r], s1 = o_rp[r + 1];
+      cur.assign(ptr.begin() + s0, ptr.begin() + s1);
+      for (int32_t sidx = s0; sidx < s1; ++sidx) ps[o_ci[sidx]] = sidx;
+      for (int32_t k = x_rp[r]; k < x_rp[r + 1]; ++k) {
+        const int32_t j = x_ci[k];
+        for (int32_t q = y_rp[j]; q < y_rp[j + 1]; ++q) {
+          const uint32_t code = (static_cast<uint32_t>(k - x_rp[r]) << bl) | static_cast<uint32_t>(q - y_rp[j]);
+          const int32_t at = cur[ps[y_ci[q]] - s0]++;
+          std::memcpy(&codes[static_cast<size_t>(at) * width], &code, width);  // little endian
+        }
+      }
+    }
+  });
+  out.width = width;
+  out.shift = bl;
+  upload(out.ptr, ptr);
+  upload(out.codes, codes);
+}
+
+// Inside every group of `per` (<= 256) consecutive output blocks, the block offsets
+// ordered by descending number of contributions (stable).
+std::vector<uint8_t> count_order(const std::vector<int32_t>& ptr, int per) {
+  const int64_t n = static_cast<int64_t>(ptr.size()) - 1;
+  std::vector<uint8_t> out(static_cast<size_t>(n));
+  std::vector<int> idx;
+  for (int64_t g = 0; g < n; g += per) {
+    const int m = static_cast<int>(std::min<int64_t>(per, n - g));
+    idx.resize(m);
+    for (int t = 0; t < m; ++t) idx[t] = t;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+      return (ptr[g + a + 1] - ptr[g + a]) > (ptr[g + b + 1] - ptr[g + b]);
+    });
+    for (int t = 0; t < m; ++t) out[g + t] = static_cast<uint8_t>(idx[t]);
+  }
+  return out;
+}
+
+std::vector<uint8_t> identity_order(size_t n, int per) {
+  std::vector<uint8_t> out(n);
+  for (size_t t = 0; t < n; ++t) out[t] = static_cast<uint8_t>(t % per);
+  return out;
+}
+
+// Row of the first output block of every group of `per` consecutive blocks.
+std::vector<int32_t> first_rows(const std::vector<int32_t>& rp, int per) {
+  const int64_t nnz = rp.back();
+  std::vector<int32_t> out(static_cast<size_t>((nnz + per - 1) / per) + 1, 0);
+  int32_t row = 0;
+  const int32_t nr = static_cast<int32_t>(rp.size()) - 1;
+  for (size_t w = 0; w + 1 < out.size(); ++w) {
+    const int64_t s0 = static_cast<int64_t>(w) * per;
+    while (row < nr && rp[row + 1] <= s0) ++row;
+    out[w] = row;
+  }
+  out.back() = std::max(nr - 1, 0);  // bound for the last group
+  return out;
+}
+
+}  // namespace
+
 }  // namespace blk
 
 using namespace blk;
@@ -224,6 +718,27 @@ int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream) {
   plan->ap_val.alloc(apci.size() * static_cast<size_t>(P->br) * P->bc * acc_size);
   upload(plan->ap_rowptr, aprp);
   upload(plan->ap_colidx, apci);
+  if (!std::getenv("BLKAMG_PTAP_SEARCH")) {
+    build_pairs(A->nbr, P->nbc, A->h_rowptr, A->h_colidx, P->h_rowptr, P->h_colidx, aprp, apci, true, plan->ap_pairs);
+    build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, crp, cci, true, plan->c_pairs);
+    plan->ap_nslots = static_cast<int64_t>(apci.size());
+    upload(plan->ap_slot_row0, first_rows(aprp, kBlock));
+    upload(plan->c_slot_row0, first_rows(crp, kBlock));
+    // tuning switches (experiments): BLKAMG_PTAP_TUNE="ap_sort,c_sort,ap_novec,c_novec"
+    const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
+    const std::string tn = tune ? tune : "ap_sort";
+    auto has = [&](const char* f) { return tn.find(f) != std::string::npos; };
+    plan->ap_vec = !has("ap_novec");
+    plan->c_vec = !has("c_novec");
+    if (plan->ap_pairs.width) {
+      std::vector<int32_t> hp = download(plan->ap_pairs.ptr.p, plan->ap_pairs.ptr.n);
+      upload(plan->ap_perm, has("ap_sort") ? count_order(hp, kBlock) : identity_order(hp.size() - 1, kBlock));
+    }
+    if (plan->c_pairs.width) {
+      std::vector<int32_t> hp = download(plan->c_pairs.ptr.p, plan->c_pairs.ptr.n);
+      upload(plan->c_perm, has("c_sort") ? count_order(hp, kBlock) : identity_order(hp.size() - 1, kBlock));
+    }
+  }
   auto Cm = make_owned(P->nbc, P->nbc, P->bc, P->bc, A->dtype, std::move(crp), std::move(cci));
   Cm->ext = plan;
   HIP_CHECK(hipStreamSynchronize(s));

@@ -172,3 +172,23 @@ def test_ptap_errors():
     with pytest.raises(B.BlkAmgError) as e:
         B.ptap_symbolic(HA, HP)
     assert e.value.code == B.EINVAL
+
+
+def test_ptap_pair_lists_and_search_fallback_agree(monkeypatch):
+    """The symbolic phase normally precomputes per-output contribution lists; with
+    BLKAMG_PTAP_SEARCH=1 it keeps the searching kernels.  Both match the oracle."""
+    m, i, j, v, A = q1_problem(7, 3)
+    from oracle import solve
+    H = solve.setup(A, m.coords, m.dirichlet, solve.Options(coarse_eq_limit=50))
+    P = H.levels[0].P
+    HA, _ = to_device_bsr(A)
+    HP, _ = to_device_bsr(P)
+    want = S.ptap(A, P)
+    C1 = B.ptap_symbolic(HA, HP)
+    B.ptap_numeric(HA, HP, C1)
+    monkeypatch.setenv("BLKAMG_PTAP_SEARCH", "1")
+    C2 = B.ptap_symbolic(HA, HP)
+    B.ptap_numeric(HA, HP, C2)
+    g1, g2 = from_device_bsr(C1), from_device_bsr(C2)
+    assert rel2(g1.val, want.val) <= 1e-12 and rel2(g2.val, want.val) <= 1e-12
+    assert np.array_equal(g1.val, g2.val)   # same summation order in both kernels
