@@ -128,6 +128,15 @@ int bsr_spmv_t(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
  * with P F32 or BF16.  Sync (host pattern work).  *C must be destroyed with
  * bsr_destroy. */
 int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream);
+/* As ptap_symbolic, with flags:
+ *   BLKAMG_PTAP_SYMMETRIC - the caller guarantees that A is symmetric (A_ij = A_ji^T),
+ *     as for the SPD operators of an AMG hierarchy; then A_c is symmetric, and
+ *     ptap_numeric computes only its blocks with column >= row and stores each
+ *     off-diagonal one a second time, transposed.  Results on a non-symmetric A are
+ *     undefined (the lower triangle mirrors the upper one).
+ * Unknown flags are EINVAL. */
+#define BLKAMG_PTAP_SYMMETRIC 1
+int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream);
 /* Numeric phase: C.values = P^T A P on the fixed pattern.  If P's value stamp
  * differs from the one cached, the prolongator-side cache (transpose values) is
  * refreshed first on the stream; if P's or A's block count changed, returns

@@ -59,6 +59,7 @@ _SIG = {
     "bsr_spmv": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_spmv_t": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
+    "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
     "ptap_numeric": (C.c_int, [_p, _p, _p, _p]),
     "coo_plan_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, C.c_int, C.POINTER(_p), C.POINTER(_p)]),
     "coo_plan_destroy": (C.c_int, [_p]),
@@ -213,6 +214,15 @@ def bsr_spmv_t(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
 def ptap_symbolic(A: Bsr, P: Bsr, stream=None) -> Bsr:
     h = _p()
     _check(_lib.ptap_symbolic(A.h, P.h, C.byref(h), _stream(stream)), "ptap_symbolic")
+    return Bsr(h, keep=(A, P))
+
+
+PTAP_SYMMETRIC = 1
+
+
+def ptap_symbolic_ex(A: Bsr, P: Bsr, flags: int, stream=None) -> Bsr:
+    h = _p()
+    _check(_lib.ptap_symbolic_ex(A.h, P.h, int(flags), C.byref(h), _stream(stream)), "ptap_symbolic_ex")
     return Bsr(h, keep=(A, P))
 
 

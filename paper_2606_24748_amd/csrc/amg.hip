@@ -1226,7 +1226,7 @@ int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, cons
       HIP_CHECK(hipStreamSynchronize(s));  // dagg / dpt are freed at scope exit
     }
     bsr_t C = nullptr;
-    int rc = ptap_symbolic(A, Lv.P.get(), &C, stream);
+    int rc = ptap_symbolic_ex(A, Lv.P.get(), BLKAMG_PTAP_SYMMETRIC, &C, stream);
     if (rc != BLKAMG_OK) fail(rc, std::string("ptap_symbolic: ") + blkamg_last_error());
     A_owned.reset(C);
     rc = ptap_numeric(A, Lv.P.get(), C, stream);
@@ -1253,7 +1253,7 @@ int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, cons
       Pf[l] = clone_pattern(P64, o.p_dtype);
       cast_values(P64->val, BLKAMG_F64, Pf[l]->val, o.p_dtype, static_cast<size_t>(P64->nnzb) * P64->block_elems(), s);
       bsr_t C = nullptr;
-      int rc = ptap_symbolic(Af[l].get(), Pf[l].get(), &C, stream);
+      int rc = ptap_symbolic_ex(Af[l].get(), Pf[l].get(), BLKAMG_PTAP_SYMMETRIC, &C, stream);
       if (rc != BLKAMG_OK) fail(rc, std::string("ptap_symbolic: ") + blkamg_last_error());
       Af[l + 1].reset(C);
       rc = ptap_numeric(Af[l].get(), Pf[l].get(), C, stream);

@@ -40,6 +40,11 @@ struct PtapPlan {
   DevBuf<int32_t> ap_slot_row0, c_slot_row0;  // row of the first block of each workgroup
   DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
   bool ap_vec = true, c_vec = true;
+  // symmetric mode: only blocks with column >= row are computed (upper list), each
+  // off-diagonal one is also stored transposed at its mirror position
+  bool sym = false;
+  int64_t c_nslots = 0;
+  DevBuf<int32_t> c_up_rp, c_up_idx, c_mirror;
 };
 
 namespace {
@@ -372,7 +377,9 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
                                                             const int32_t* __restrict__ y_rp, const TY* __restrict__ y_v,
                                                             const int32_t* __restrict__ o_rp,
                                                             const int32_t* __restrict__ pp, const CT* __restrict__ codes,
-                                                            int shift, void* __restrict__ out) {
+                                                            int shift, void* __restrict__ out,
+                                                            const int32_t* __restrict__ out_idx,
+                                                            const int32_t* __restrict__ mirror) {
   // kIsAP: X = A (BR x BR), Y = P (BR x BC), out AP (BR x BC) in TA
   // else : X = R (BC x BR), Y = AP (BR x BC), out C (BC x BC) in the type of A
   constexpr int XR = kIsAP ? BR : BC;  // rows of an X block
@@ -437,10 +444,24 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
 #pragma unroll
     for (int t = 0; t < OR * BC; ++t) o[t] = acc[t];
   } else {
+    // symmetric mode: slot sidx is the out_idx[sidx]-th block of C; its transpose
+    // also goes to block mirror[sidx] (-1 on the diagonal)
     using TC = typename std::conditional<sizeof(TA) == 8, double, float>::type;
-    TC* o = static_cast<TC*>(out) + static_cast<size_t>(sidx) * (OR * BC);
+    const int64_t oi = out_idx ? out_idx[sidx] : sidx;
+    TC* o = static_cast<TC*>(out) + static_cast<size_t>(oi) * (OR * BC);
 #pragma unroll
     for (int t = 0; t < OR * BC; ++t) st(o + t, acc[t]);
+    if (mirror) {
+      const int mi = mirror[sidx];
+      if (mi >= 0) {
+        TC* o2 = static_cast<TC*>(out) + static_cast<size_t>(mi) * (OR * BC);
+#pragma unroll
+        for (int r = 0; r < OR; ++r) {
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) st(o2 + cc * OR + r, acc[r * BC + cc]);
+        }
+      }
+    }
   }
 }
 
@@ -458,20 +479,22 @@ void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap,
   pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, 0, s>>>(                                        \
       ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
       static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_pairs.ptr.p,                                             \
-      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap)
+      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr)
   if (vec) BLK_APK(true); else BLK_APK(false);
 #undef BLK_APK
 }
 
 template <int BR, int BC, class TA_, class TP, class TA, class CT>
 void launch_rap_pairs(const PtapPlan& pl, const bsr_s* R, const bsr_s* C, const TA* ap, hipStream_t s) {
-  const int64_t ns = C->nnzb;
+  const int64_t ns = pl.sym ? pl.c_nslots : C->nnzb;
   const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
   if (grid == 0) return;
+  const int32_t* orp = pl.sym ? pl.c_up_rp.p : C->rowptr;
 #define BLK_RAPK(V)                                                                                                  \
   pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V><<<grid, kBlock, 0, s>>>(                                        \
       ns, C->nbr, pl.c_slot_row0.p, pl.c_perm.p, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, \
-      ap, C->rowptr, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val)
+      ap, orp, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val,           \
+      pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr)
   if (pl.c_vec) BLK_RAPK(true); else BLK_RAPK(false);
 #undef BLK_RAPK
 }
@@ -585,18 +608,22 @@ void build_pairs(int32_t nrows, int32_t ncols, const std::vector<int32_t>& x_rp,
   const size_t nout = o_ci.size();
   std::vector<int32_t> cnt(nout + 1, 0);
   std::vector<int64_t> max_hi(nth, 0), max_lo(nth, 0);
-  std::vector<std::vector<int32_t>> pos(nth);
-  // pass 1: counts and ranges
+  std::vector<std::vector<int32_t>> pos(nth), tag(nth);
+  // pass 1: counts and ranges (contributions to columns outside the output row are
+  // skipped: the output pattern may be a subset of the product pattern)
   parallel_rows(nrows, [&](int32_t r0, int32_t r1, int tid) {
     auto& ps = pos[tid];
+    auto& tg = tag[tid];
     ps.assign(static_cast<size_t>(ncols), -1);
+    tg.assign(static_cast<size_t>(ncols), -1);
     for (int32_t r = r0; r < r1; ++r) {
-      for (int32_t sidx = o_rp[r]; sidx < o_rp[r + 1]; ++sidx) ps[o_ci[sidx]] = sidx;
+      for (int32_t sidx = o_rp[r]; sidx < o_rp[r + 1]; ++sidx) { ps[o_ci[sidx]] = sidx; tg[o_ci[sidx]] = r; }
       for (int32_t k = x_rp[r]; k < x_rp[r + 1]; ++k) {
         const int32_t j = x_ci[k];
-        max_hi[tid] = std::max<int64_t>(max_hi[tid], k - x_rp[r]);
         for (int32_t q = y_rp[j]; q < y_rp[j + 1]; ++q) {
+          if (tg[y_ci[q]] != r) continue;
           cnt[ps[y_ci[q]] + 1]++;
+          max_hi[tid] = std::max<int64_t>(max_hi[tid], k - x_rp[r]);
           max_lo[tid] = std::max<int64_t>(max_lo[tid], q - y_rp[j]);
         }
       }
@@ -619,14 +646,17 @@ void build_pairs(int32_t nrows, int32_t ncols, const std::vector<int32_t>& x_rp,
   // pass 2: fill (each row writes only its own output range)
   parallel_rows(nrows, [&](int32_t r0, int32_t r1, int tid) {
     auto& ps = pos[tid];
+    auto& tg = tag[tid];
+    std::fill(tg.begin(), tg.end(), -1);
     std::vector<int32_t> cur;
     for (int32_t r = r0; r < r1; ++r) {
       const int32_t s0 = o_rp[r], s1 = o_rp[r + 1];
       cur.assign(ptr.begin() + s0, ptr.begin() + s1);
-      for (int32_t sidx = s0; sidx < s1; ++sidx) ps[o_ci[sidx]] = sidx;
+      for (int32_t sidx = s0; sidx < s1; ++sidx) { ps[o_ci[sidx]] = sidx; tg[o_ci[sidx]] = r; }
       for (int32_t k = x_rp[r]; k < x_rp[r + 1]; ++k) {
         const int32_t j = x_ci[k];
         for (int32_t q = y_rp[j]; q < y_rp[j + 1]; ++q) {
+          if (tg[y_ci[q]] != r) continue;
           const uint32_t code = (static_cast<uint32_t>(k - x_rp[r]) << bl) | static_cast<uint32_t>(q - y_rp[j]);
           const int32_t at = cur[ps[y_ci[q]] - s0]++;
           std::memcpy(&codes[static_cast<size_t>(at) * width], &code, width);  // little endian
@@ -687,8 +717,11 @@ using namespace blk;
 
 extern "C" {
 
-int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream) {
+int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream) { return ptap_symbolic_ex(A, P, 0, C, stream); }
+
+int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
   BLK_API_BEGIN
+  BLK_REQUIRE((flags & ~BLKAMG_PTAP_SYMMETRIC) == 0, BLKAMG_EINVAL, "unknown ptap flags");
   BLK_REQUIRE(A != nullptr && P != nullptr && C != nullptr, BLKAMG_EINVAL, "NULL argument");
   *C = nullptr;
   BLK_REQUIRE(A->br == A->bc && A->br == P->br, BLKAMG_EINVAL, "A must be square-blocked with bs = P.bs_r");
@@ -720,10 +753,40 @@ int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream) {
   upload(plan->ap_colidx, apci);
   if (!std::getenv("BLKAMG_PTAP_SEARCH")) {
     build_pairs(A->nbr, P->nbc, A->h_rowptr, A->h_colidx, P->h_rowptr, P->h_colidx, aprp, apci, true, plan->ap_pairs);
-    build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, crp, cci, true, plan->c_pairs);
+    plan->sym = (flags & BLKAMG_PTAP_SYMMETRIC) != 0;
+    std::vector<int32_t> orp = crp, oci = cci;  // output blocks of the R*AP pass
+    if (plan->sym) {
+      // upper blocks (column >= row), their index in C and the index of the mirror
+      std::vector<int32_t> uidx, mir;
+      orp.assign(crp.size(), 0);
+      oci.clear();
+      for (int32_t a = 0; a + 1 < static_cast<int32_t>(crp.size()); ++a) {
+        for (int32_t t = crp[a]; t < crp[a + 1]; ++t) {
+          const int32_t c = cci[t];
+          if (c < a) continue;
+          int32_t m = -1;
+          if (c != a) {
+            const auto b0 = cci.begin() + crp[c], b1 = cci.begin() + crp[c + 1];
+            const auto it = std::lower_bound(b0, b1, a);
+            BLK_REQUIRE(it != b1 && *it == a, BLKAMG_EINVAL, "coarse pattern is not symmetric");
+            m = static_cast<int32_t>(it - cci.begin());
+          }
+          oci.push_back(c);
+          uidx.push_back(t);
+          mir.push_back(m);
+        }
+        orp[a + 1] = static_cast<int32_t>(oci.size());
+      }
+      plan->c_nslots = static_cast<int64_t>(oci.size());
+      upload(plan->c_up_rp, orp);
+      upload(plan->c_up_idx, uidx);
+      upload(plan->c_mirror, mir);
+    }
+    build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, orp, oci, true, plan->c_pairs);
+    if (!plan->c_pairs.width) plan->sym = false;  // the searching kernel computes every block
     plan->ap_nslots = static_cast<int64_t>(apci.size());
     upload(plan->ap_slot_row0, first_rows(aprp, kBlock));
-    upload(plan->c_slot_row0, first_rows(crp, kBlock));
+    upload(plan->c_slot_row0, first_rows(orp, kBlock));
     // tuning switches (experiments): BLKAMG_PTAP_TUNE="ap_sort,c_sort,ap_novec,c_novec"
     const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
     const std::string tn = tune ? tune : "ap_sort";

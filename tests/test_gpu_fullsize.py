@@ -1,0 +1,135 @@
+"""Parity at the benchmark size: Q1 elasticity on 128^3 elements (6,440,067 dofs), the
+configuration bench.py times.  The oracle cannot run this problem whole, so the checks
+are (a) sampled outputs the oracle computes one by one (assembled block rows, SpMV
+rows) and (b) properties that hold at any size (aggregation closed form, the Galerkin
+identity A_c v = P^T A P v on every level, symmetry of A_c, PCG's true residual)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import sparse as S  # noqa: E402
+from paper_2606_24748_amd import blkamg as B  # noqa: E402
+from tests.gpu_util import rel2  # noqa: E402
+
+N = 128
+
+
+@pytest.fixture(scope="module")
+def big():
+    print(f"full-size problem n={N}", flush=True)
+    m = synth.make_mesh(N)
+    i, j = synth.coo_indices(m)
+    lam, mu = synth.lame(*synth.materials(m.n_elem, 11))
+    vals = synth.coo_values_torch(m, lam, mu, "cuda")
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, vals, B.INSERT, HA)
+    torch.cuda.synchronize()
+    yield dict(m=m, i=i, j=j, lam=lam, mu=mu, vals=vals, plan=plan, HA=HA)
+    del vals
+    torch.cuda.empty_cache()
+
+
+def _oracle_rows(d, rows):
+    """Oracle assembly of the given block rows only (the COO sum is row-local), from
+    the same input stream the GPU assembled."""
+    m = d["m"]
+    i, j = d["i"], d["j"]
+    k = np.nonzero(np.isin(i, rows))[0]
+    v = d["vals"][torch.as_tensor(k).cuda()].cpu().numpy()
+    return S.coo_assemble(m.n_nodes, m.n_nodes, i[k], j[k], v)
+
+
+def test_fullsize_assembly_and_spmv_sampled_rows(big):
+    m, HA = big["m"], big["HA"]
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, m.n_nodes, 200), [0, 1, m.n_nodes - 1, 129, 130]]))
+    Ao = _oracle_rows(big, rows)
+    rp, ci, v = HA.arrays()
+    rp, ci = rp.cpu().numpy(), ci.cpu().numpy()
+    for r in rows:
+        k0, k1 = rp[r], rp[r + 1]
+        o0, o1 = Ao.rowptr[r], Ao.rowptr[r + 1]
+        assert np.array_equal(ci[k0:k1], Ao.colidx[o0:o1])
+        assert np.array_equal(v[k0:k1].cpu().numpy(), Ao.val[o0:o1])  # same summation order
+    x = rng.uniform(-1, 1, m.n_dof)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        if dt == torch.float64:
+            H = HA
+        else:
+            H = B.bsr_create(m.n_nodes, m.n_nodes, 3, 3, rp_t := torch.as_tensor(rp).cuda(),
+                             ci_t := torch.as_tensor(ci).cuda(), v32 := v.float().contiguous())
+        y = torch.zeros(m.n_dof, dtype=dt, device="cuda")
+        B.bsr_spmv(H, 1.0, torch.as_tensor(x, dtype=dt).cuda(), 0.0, y)
+        xs = torch.as_tensor(x, dtype=dt).double().numpy()
+        want = S.spmv_rows(Ao, xs, rows).reshape(-1)
+        got = y.double().cpu().numpy().reshape(-1, 3)[rows].reshape(-1)
+        assert rel2(got, want) <= tol
+
+
+def _lattice_aggregates(m, n):
+    def axis(lo, hi):
+        p = np.arange(lo, hi + 1)
+        nr = (hi - lo) // 3 + 1
+        return np.minimum((p - lo + 1) // 3, nr - 1), nr
+    qx, nx = axis(1, n)
+    qy, ny = axis(0, n)
+    g = np.rint(m.coords * n).astype(int)
+    want = np.full(m.n_nodes, -1)
+    free = g[:, 0] >= 1
+    want[free] = qx[g[free, 0] - 1] + nx * (qy[g[free, 1]] + ny * qy[g[free, 2]])
+    return want
+
+
+@pytest.mark.parametrize("hier,pdt", [(B.F64, B.F64), (B.F32, B.F32)])
+def test_fullsize_hierarchy_galerkin_identity_and_pcg(big, hier, pdt):
+    m, HA = big["m"], big["HA"]
+    o = B.blkamg_opts_default()
+    o.hier_dtype, o.p_dtype = hier, pdt
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    assert M.num_levels() == 4
+    assert np.array_equal(M.aggregates(0), _lattice_aggregates(m, N))
+    sizes = [M.level(l)[0].info() for l in range(4)]
+    assert [s["nbr"] * s["bs_r"] for s in sizes] == [6440067, 477042, 20250, 750]
+    assert [s["nnzb"] for s in sizes] == [56638591, 2048383, 79507, 2197]
+    # hot recompute on new values, then the Galerkin identity on every level
+    lam2, mu2 = synth.lame(*synth.materials(m.n_elem, 1011))
+    B.coo_assemble_blocked(big["plan"], synth.coo_values_torch(m, lam2, mu2, "cuda"), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    B.amg_smoother_refresh(M)
+    tdt = torch.float64 if hier == B.F64 else torch.float32
+    tol = 1e-12 if hier == B.F64 else 2e-5
+    rng = np.random.default_rng(1)
+    for l in range(3):
+        Al, Pl = M.level(l)
+        Ac, _ = M.level(l + 1)
+        nf = Al.info()["nbr"] * Al.info()["bs_r"]
+        nc = Ac.info()["nbr"] * 6
+        vc = torch.as_tensor(rng.uniform(-1, 1, nc), dtype=tdt).cuda()
+        pv = torch.zeros(nf, dtype=tdt, device="cuda")
+        B.bsr_spmv(Pl, 1.0, vc, 0.0, pv)
+        apv = torch.zeros_like(pv)
+        B.bsr_spmv(Al, 1.0, pv, 0.0, apv)
+        lhs = torch.zeros(nc, dtype=tdt, device="cuda")
+        B.bsr_spmv_t(Pl, 1.0, apv, 0.0, lhs)
+        rhs = torch.zeros(nc, dtype=tdt, device="cuda")
+        B.bsr_spmv(Ac, 1.0, vc, 0.0, rhs)
+        assert rel2(rhs.double().cpu().numpy(), lhs.double().cpu().numpy()) <= tol
+        # symmetry of the coarse operator: u^T A_c v = v^T A_c u
+        uc = torch.as_tensor(rng.uniform(-1, 1, nc), dtype=tdt).cuda()
+        au = torch.zeros_like(uc)
+        B.bsr_spmv(Ac, 1.0, uc, 0.0, au)
+        s1 = float((vc.double() * au.double()).sum())
+        s2 = float((uc.double() * rhs.double()).sum())
+        assert abs(s1 - s2) <= tol * 10 * abs(s1)
+    b = torch.as_tensor(synth.rhs(m, 12)).cuda()
+    x = torch.zeros_like(b)
+    code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+    assert code == B.OK and rel <= 1e-8 and 10 <= it <= 40
+    r = b.clone()
+    B.bsr_spmv(HA, -1.0, x, 1.0, r)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 2e-8
+    print(f"hier={hier} pcg its={it} relres={rel:.2e}", flush=True)

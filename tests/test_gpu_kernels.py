@@ -192,3 +192,29 @@ def test_ptap_pair_lists_and_search_fallback_agree(monkeypatch):
     g1, g2 = from_device_bsr(C1), from_device_bsr(C2)
     assert rel2(g1.val, want.val) <= 1e-12 and rel2(g2.val, want.val) <= 1e-12
     assert np.array_equal(g1.val, g2.val)   # same summation order in both kernels
+
+
+@pytest.mark.parametrize("bs", [3, 6])
+def test_ptap_symmetric_mode(bs):
+    """BLKAMG_PTAP_SYMMETRIC computes the upper blocks and mirrors them: same values
+    as the oracle within 1e-12, and the result is exactly symmetric."""
+    rp, ci, v = synth.random_spd_bsr(300, bs, seed=21, max_per_row=10)
+    A = S.Bsr(300, 300, bs, bs, rp.astype(np.int64), ci.astype(np.int64), v)
+    P = _rand(300, 41, bs, 6, seed=22, max_per_row=4)
+    HA, _ = to_device_bsr(A)
+    HP, _ = to_device_bsr(P)
+    HC = B.ptap_symbolic_ex(HA, HP, B.PTAP_SYMMETRIC)
+    B.ptap_numeric(HA, HP, HC)
+    want = S.ptap(A, P)
+    got = from_device_bsr(HC)
+    assert np.array_equal(got.rowptr, want.rowptr) and np.array_equal(got.colidx, want.colidx)
+    assert rel2(got.val, want.val) <= 1e-12
+    rows = got.block_rows()
+    pos = {(int(r), int(c)): t for t, (r, c) in enumerate(zip(rows, got.colidx))}
+    for t, (r, c) in enumerate(zip(rows, got.colidx)):
+        if r != c:   # mirrored: exact
+            assert np.array_equal(got.val[t], got.val[pos[(int(c), int(r))]].T)
+        else:        # computed directly: symmetric to rounding
+            assert np.abs(got.val[t] - got.val[t].T).max() <= 1e-13 * np.abs(got.val[t]).max()
+    with pytest.raises(B.BlkAmgError):
+        B.ptap_symbolic_ex(HA, HP, 8)
