@@ -54,6 +54,9 @@ def parse_args(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only assemble the fine operator and run the SpMV probe and the copy calibration")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve section")
+    ap.add_argument("--batch-eager", action="store_true",
+                    help="also time the batched CG launched eagerly (no graph replay)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-n", type=int, default=32, help=argparse.SUPPRESS)
     return ap.parse_args(argv)
@@ -153,6 +156,70 @@ def copy_probe(torch, stream, nbytes=1 << 30, reps=10):
     ms = e0.elapsed_time(e1) / reps
     return {"bytes_read": nbytes, "bytes_written": nbytes, "avg_launch_ms": ms,
             "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def run_batch(args, B, torch, dev, stream):
+    """Batch of 24 independent Q1 instances, edge n ~ U{16..48} (rng seed 100), material
+    seeds 200+t (redraw 1200+t), 8 right-hand sides each (seed 300+t), FP32
+    hierarchies, FP64 CG; one step = assemble + Galerkin recompute + refresh + batched
+    CG over all 192 systems with a graph-replayed iteration block."""
+    import numpy as np
+
+    import synth
+
+    t0 = time.perf_counter()
+    sizes = synth.batch_sizes()
+    bt = synth.make_batch(sizes, nrhs=8)
+    vals = [synth.batch_values_torch(bt, dev)]
+    mats2 = [synth.lame(*synth.materials(m.n_elem, 1200 + t)) for t, m in enumerate(bt["meshes"])]
+    vals.append(torch.cat([synth.coo_values_torch(m, lam, mu, dev) for m, (lam, mu) in zip(bt["meshes"], mats2)]))
+    b = torch.as_tensor(bt["b"], device=dev)
+    n_nodes = bt["n_nodes"]
+    n_dof = 3 * n_nodes
+    log(f"[batch] {len(sizes)} instances, sizes {sizes.tolist()}, {n_dof} dofs ({time.perf_counter() - t0:.1f}s)")
+    plan, HA = B.coo_plan_create(n_nodes, n_nodes, 3, 3, bt["i"], bt["j"])
+    B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
+    del bt["i"], bt["j"]
+    res = {"instances": int(len(sizes)), "sizes": sizes.tolist(), "nrhs": 8, "dofs": int(n_dof),
+           "fine_nnzb": HA.info()["nnzb"]}
+    modes = [("graph", 4)] + ([("eager", 0)] if args.batch_eager else [])
+    for name, gi in modes:
+        o = B.blkamg_opts_default()
+        o.hier_dtype, o.p_dtype = B.F32, B.F32
+        o.pcg_graph_iters = gi
+        o.autotune_nrhs = 8
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = B.amg_setup_batched(HA, bt["row0"], bt["coords"], bt["dirichlet"], o)
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros_like(b)
+        rec = []
+        for s in range(args.warmup + args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            vi = (s + 1) % 2
+            ev[0].record(stream)
+            B.coo_assemble_blocked(plan, vals[vi], B.INSERT, HA)
+            ev[1].record(stream)
+            B.amg_galerkin_recompute(M)
+            ev[2].record(stream)
+            B.amg_smoother_refresh(M)
+            ev[3].record(stream)
+            code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000, nrhs=8)
+            ev[4].record(stream)
+            ev[4].synchronize()
+            ph = [ev[k].elapsed_time(ev[k + 1]) for k in range(4)]
+            if s >= args.warmup:
+                rec.append({"coo_ms": ph[0], "ptap_ms": ph[1], "refresh_ms": ph[2], "pcg_ms": ph[3],
+                            "its_max": int(its.max()), "its_mean": float(its.mean()), "status": code,
+                            "relres_max": float(rel.max())})
+            log(f"[batch/{name}] step {s}: coo {ph[0]:.2f} ms, ptap {ph[1]:.2f} ms, refresh {ph[2]:.2f} ms, "
+                f"pcg {ph[3]:.1f} ms (its {int(its.min())}..{int(its.max())}, relres max {float(rel.max()):.1e})")
+        med = {k: statistics.median(r[k] for r in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
+        res[name] = {"pcg_graph_iters": gi, "setup_s": t_setup, "median_ms": med, "steps": rec,
+                     "systems_per_s": 192.0 / (med["pcg_ms"] * 1e-3), "levels": M.num_levels()}
+        del M
+        torch.cuda.synchronize()
+    return res
 
 
 def main(argv=None):
@@ -276,6 +343,11 @@ def main(argv=None):
         torch.cuda.synchronize()
 
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+    batch = None
+    if not args.no_batch:
+        del plan, HA, vals
+        torch.cuda.empty_cache()
+        batch = run_batch(args, B, torch, dev, stream)
     achieved, spmv_b, spmv_ms = probe["achieved_GBs"], probe["bytes_per_launch"], probe["avg_launch_ms"]
 
     head = "mixed" if "mixed" in results else variants[0]
@@ -310,6 +382,7 @@ def main(argv=None):
                      "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
         "cpu_baseline": cpu,
         "variants": results,
+        "batch": batch,
         "coo_plan_s": t_plan,
     }
     if "fp64" in results and head != "fp64":

@@ -115,6 +115,14 @@ int bsr_spmv(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
  * changed since they were last copied.  Async afterwards. */
 int bsr_spmv_t(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
                int vec_dtype, int32_t nrhs, void* stream);
+/* Autotuner of the blocked SpMV (paper §4.2 kernel, shapes for gfx950): times every
+ * compiled lane shape (G lanes per block row in {8,16,32,64} x U in {1,2} blocks per
+ * lane per step) of y = A x with zero vectors of `vec_dtype` and `nrhs` (1 or 8)
+ * columns on the stream with device events, and stores the fastest in the handle;
+ * later SpMVs of A with that many columns (bsr_spmv, and the fused hierarchy
+ * kernels) use it.  *code = G * 8 + U (may be NULL).  Sync; allocates two
+ * temporary vectors. */
+int bsr_autotune(bsr_t A, int vec_dtype, int32_t nrhs, void* stream, int32_t* code);
 
 /* ==========================================================================
  * Galerkin coarse operator A_c = P^T A P (paper §2.1, §3.1, §3.5)
@@ -186,6 +194,12 @@ typedef struct {
   double omega_scale;       /* prolongator-smoothing weight omega = omega_scale / lambda_hat, 4/3 */
   int32_t hier_dtype;       /* F64 or F32: type of the level operators, smoother and V-cycle */
   int32_t p_dtype;          /* type of the stored prolongators: F64 (with F64), F32 or BF16 (with F32) */
+  int32_t pcg_graph_iters;  /* batched CG (several instances or nrhs = 8): iterations per
+                               replay of a captured HIP graph; 0 = launch eagerly.
+                               Default 4 (0..64) */
+  int32_t autotune_nrhs;    /* 0: heuristic SpMV lane shapes; 1 or 8: at setup, time every
+                               compiled shape of each hierarchy SpMV (and of A0) for that
+                               many right-hand sides and keep the fastest.  Default 0 */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -211,22 +225,46 @@ int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
  * and must outlive the hierarchy.  Sync; allocates. */
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet,
               const blkamg_opts* opts, void* stream, amg_t* out);
+/* Hierarchy of a batch of independent problems given as one block-diagonal A0:
+ * instance t owns block rows (and columns) [h_inst_row0[t], h_inst_row0[t+1]),
+ * h_inst_row0 has n_inst + 1 entries from 0 to A0.nbr, and no stored block may
+ * couple two instances (EINVAL otherwise).  Each instance is coarsened exactly as
+ * amg_setup would coarsen it alone (own aggregates, own lambda_hat per level, own
+ * coarsest level and Cholesky factor); one kernel launch serves all instances of
+ * a level.  Instances with at most coarse_eq_limit dofs must come last.  On every
+ * level the rows of the instances still smoothed there come first, then those of
+ * the instances whose coarsest level it is (amg_instance_rows tells where each
+ * instance lives).  Sync; allocates. */
+int amg_setup_batched(bsr_t A0, int32_t n_inst, const int32_t* h_inst_row0,
+                      const double* h_coords, const uint8_t* h_dirichlet,
+                      const blkamg_opts* opts, void* stream, amg_t* out);
 int amg_destroy(amg_t M);
 int amg_num_levels(amg_t M, int32_t* n_levels);
+/* Number of instances (1 for amg_setup). */
+int amg_num_instances(amg_t M, int32_t* n_inst);
+/* Where each instance lives on `level` (host arrays of n_inst entries, any may be
+ * NULL): first block row, number of block rows, and state 0 = the instance has no
+ * such level, 1 = smoothed there, 2 = this is its coarsest level (dense solve). */
+int amg_instance_rows(amg_t M, int32_t level, int32_t* h_row0, int32_t* h_nrows,
+                      int32_t* h_state);
 /* Level operators (library-owned; level 0 is A0 itself for F64 hierarchies and a
  * library-owned F32 copy for F32 hierarchies) and prolongators (NULL on the
  * coarsest level).  Handles remain owned by the hierarchy. */
 int amg_level(amg_t M, int32_t level, bsr_t* A, bsr_t* P);
-/* Host copy of the aggregates of `level` (int32[nbr of that level]). */
+/* Host copy of the aggregates of `level`: one id (row of level + 1) per smoothed
+ * row, int32[number of smoothed rows of that level] (all rows for one instance);
+ * -1 for Dirichlet rows. */
 int amg_aggregates(amg_t M, int32_t level, int32_t* h_agg);
-/* Host copy of lambda_hat per level (double[n_levels-1]).  Sync. */
+/* Host copy of lambda_hat, double[n_levels - 1][n_inst] (level-major); 0 where the
+ * instance is not smoothed on that level.  Sync. */
 int amg_lambdas(amg_t M, double* h_lam);
 /* Hot Galerkin recompute with reused interpolation (paper §3.1, §3.5): after A0's
  * values changed, recompute every coarse operator with ptap_numeric on the fixed
  * patterns (F32 hierarchies first cast A0 to their F32 copy).  Async, no allocation. */
 int amg_galerkin_recompute(amg_t M, void* stream);
 /* Refresh the smoother data after a recompute: block-diagonal inverses,
- * lambda_hat (Lanczos, or taken from h_lambda[level] when h_lambda != NULL),
+ * lambda_hat (Lanczos, or taken from h_lambda[level * n_inst + instance] when
+ * h_lambda != NULL; entries of instances not smoothed on a level are ignored),
  * Chebyshev coefficients and the coarsest Cholesky factor.  Returns ENOTSPD if the
  * factorisation meets a non-positive pivot (sync check at the end).  Sync. */
 int amg_smoother_refresh(amg_t M, const double* h_lambda, void* stream);
@@ -234,16 +272,24 @@ int amg_smoother_refresh(amg_t M, const double* h_lambda, void* stream);
 /* One V-cycle from a zero guess, z = M^-1 r (paper §2.1): Chebyshev/point-block-
  * Jacobi pre-smoothing, residual, restriction with P^T, recursion, prolongation,
  * post-smoothing, coarsest solve with the Cholesky factor.  d_r, d_z: F64
- * [n_dof(A0)][nrhs], nrhs in 1..8 (F32 hierarchies convert at entry and exit).
- * Async. */
+ * [n_dof(A0)][nrhs], nrhs 1 or 8 (F32 hierarchies convert at entry and exit).
+ * Async (the first call with nrhs = 8 allocates the wider work vectors). */
 int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* stream);
 
 /* Preconditioned CG on A x = b (the CG accelerator of paper §4.1) from x0 = 0 with
  * M = one V-cycle; stops when the recurrence residual satisfies
  * ||r||_2 <= rtol ||b||_2 (unpreconditioned norm, paper §4.1) or after maxit
- * iterations.  A: F64, n_dof = A0's; d_b, d_x: F64 [n_dof] (nrhs must be 1).
- * *iters = number of solution updates; *relres = ||r||/||b||.  Returns ENOCONV at
- * maxit, EBREAKDOWN if p^T A p <= 0.  Sync (one 8-byte read per iteration). */
+ * iterations.  A: F64, n_dof = A0's; d_b, d_x: F64 [n_dof][nrhs], nrhs 1 or 8.
+ * Every (instance, column) pair is its own system with its own CG scalars and
+ * stopping test; a system that stopped is frozen while the others go on.
+ * iters, relres (may be NULL): [n_inst][nrhs] number of solution updates and
+ * ||r||/||b|| (0 for b = 0).  Returns ENOCONV if any system reached maxit,
+ * EBREAKDOWN if p^T A p <= 0 in any (results of the others are still written).
+ * One instance with one column: one 8-byte read per iteration.  Otherwise the
+ * stopping tests stay on the device and the host reads an 8-byte status every
+ * pcg_graph_iters iterations, each block of iterations replayed from a captured
+ * HIP graph (captured on a library stream on first use, recaptured when x, A,
+ * nrhs, rtol or maxit change).  Sync. */
 int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol,
               int32_t maxit, int32_t nrhs, int32_t* iters, double* relres, void* stream);
 

@@ -45,6 +45,8 @@ class Opts(C.Structure):
         ("omega_scale", C.c_double),
         ("hier_dtype", C.c_int32),
         ("p_dtype", C.c_int32),
+        ("pcg_graph_iters", C.c_int32),
+        ("autotune_nrhs", C.c_int32),
     ]
 
 
@@ -58,6 +60,7 @@ _SIG = {
     "bsr_arrays": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p)]),
     "bsr_spmv": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_spmv_t": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
+    "bsr_autotune": (C.c_int, [_p, C.c_int, _i32, _p, _pi32]),
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
     "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
     "ptap_numeric": (C.c_int, [_p, _p, _p, _p]),
@@ -68,8 +71,11 @@ _SIG = {
     "blkamg_opts_default": (None, [C.POINTER(Opts)]),
     "sa_aggregate": (C.c_int, [_i32, _p, _p, _p, _p, _pi32]),
     "amg_setup": (C.c_int, [_p, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
+    "amg_setup_batched": (C.c_int, [_p, _i32, _p, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
     "amg_destroy": (C.c_int, [_p]),
     "amg_num_levels": (C.c_int, [_p, _pi32]),
+    "amg_num_instances": (C.c_int, [_p, _pi32]),
+    "amg_instance_rows": (C.c_int, [_p, _i32, _p, _p, _p]),
     "amg_level": (C.c_int, [_p, _i32, C.POINTER(_p), C.POINTER(_p)]),
     "amg_aggregates": (C.c_int, [_p, _i32, _p]),
     "amg_lambdas": (C.c_int, [_p, _p]),
@@ -211,6 +217,13 @@ def bsr_spmv_t(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
            "bsr_spmv_t")
 
 
+def bsr_autotune(A: Bsr, vec_dtype=F64, nrhs=1, stream=None) -> int:
+    """Time the compiled SpMV lane shapes of A and keep the fastest; returns G*8+U."""
+    code = _i32()
+    _check(_lib.bsr_autotune(A.h, int(vec_dtype), int(nrhs), _stream(stream), C.byref(code)), "bsr_autotune")
+    return code.value
+
+
 def ptap_symbolic(A: Bsr, P: Bsr, stream=None) -> Bsr:
     h = _p()
     _check(_lib.ptap_symbolic(A.h, P.h, C.byref(h), _stream(stream)), "ptap_symbolic")
@@ -303,17 +316,32 @@ class Amg:
         _check(_lib.amg_level(self.h, l, C.byref(A), C.byref(P)), "amg_level")
         return (Bsr(A, owner=self), Bsr(P, owner=self) if P.value else None)
 
+    def num_instances(self) -> int:
+        n = _i32()
+        _check(_lib.amg_num_instances(self.h, C.byref(n)), "amg_num_instances")
+        return n.value
+
+    def instance_rows(self, l):
+        """(row0, nrows, state) per instance on level l; state 0 absent, 1 smoothed, 2 coarsest."""
+        k = self.num_instances()
+        r0, nr, st = (np.zeros(k, dtype=np.int32) for _ in range(3))
+        _check(_lib.amg_instance_rows(self.h, l, r0.ctypes.data_as(_p), nr.ctypes.data_as(_p),
+                                      st.ctypes.data_as(_p)), "amg_instance_rows")
+        return r0, nr, st
+
     def aggregates(self, l):
-        A, _ = self.level(l)
-        agg = np.empty(A.info()["nbr"], dtype=np.int32)
+        _, nr, st = self.instance_rows(l)
+        agg = np.empty(int(nr[st == 1].sum()), dtype=np.int32)
         _check(_lib.amg_aggregates(self.h, l, agg.ctypes.data_as(_p)), "amg_aggregates")
         return agg
 
     def lambdas(self):
-        lam = np.zeros(max(self.num_levels() - 1, 0))
-        if len(lam):
+        """lambda_hat [n_levels - 1] for one instance, [n_levels - 1][n_inst] for a batch."""
+        k = self.num_instances()
+        lam = np.zeros((max(self.num_levels() - 1, 0), k))
+        if lam.size:
             _check(_lib.amg_lambdas(self.h, lam.ctypes.data_as(_p)), "amg_lambdas")
-        return lam
+        return lam[:, 0] if k == 1 else lam
 
 
 def amg_setup(A0: Bsr, coords: np.ndarray, dirichlet=None, opts: Opts | None = None, stream=None) -> Amg:
@@ -327,6 +355,23 @@ def amg_setup(A0: Bsr, coords: np.ndarray, dirichlet=None, opts: Opts | None = N
     h = _p()
     _check(_lib.amg_setup(A0.h, coords.ctypes.data_as(_p), d, C.byref(o), _stream(stream), C.byref(h)),
            "amg_setup")
+    return Amg(h, keep=(A0,))
+
+
+def amg_setup_batched(A0: Bsr, inst_row0, coords: np.ndarray, dirichlet=None, opts: Opts | None = None,
+                      stream=None) -> Amg:
+    """Hierarchy of a block-diagonal batch: instance t owns block rows [inst_row0[t], inst_row0[t+1])."""
+    row0 = np.ascontiguousarray(inst_row0, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    d = None
+    dd = None
+    if dirichlet is not None:
+        dd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        d = dd.ctypes.data_as(_p)
+    o = opts or blkamg_opts_default()
+    h = _p()
+    _check(_lib.amg_setup_batched(A0.h, len(row0) - 1, row0.ctypes.data_as(_p), coords.ctypes.data_as(_p), d,
+                                  C.byref(o), _stream(stream), C.byref(h)), "amg_setup_batched")
     return Amg(h, keep=(A0,))
 
 
@@ -346,11 +391,16 @@ def vcycle_apply(M: Amg, r, z, nrhs=1, stream=None):
     _check(_lib.vcycle_apply(M.h, _ptr(r), _ptr(z), nrhs, _stream(stream)), "vcycle_apply")
 
 
-def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, stream=None):
-    """Returns (status, iterations, relative residual); status OK or ENOCONV."""
-    it = _i32()
-    rr = _f64()
-    code = _lib.pcg_solve(A.h, M.h, _ptr(b), _ptr(x), float(rtol), int(maxit), 1, C.byref(it), C.byref(rr),
-                          _stream(stream))
+def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, nrhs=1, stream=None):
+    """Returns (status, iterations, relative residual); status OK or ENOCONV.  For one
+    instance and nrhs = 1 the last two are scalars, otherwise int32 / float64 arrays
+    [n_inst][nrhs]."""
+    k = M.num_instances()
+    it = np.zeros(k * nrhs, dtype=np.int32)
+    rr = np.zeros(k * nrhs, dtype=np.float64)
+    code = _lib.pcg_solve(A.h, M.h, _ptr(b), _ptr(x), float(rtol), int(maxit), int(nrhs), it.ctypes.data_as(_pi32),
+                          rr.ctypes.data_as(C.POINTER(_f64)), _stream(stream))
     _check(code, "pcg_solve", allow=(OK, ENOCONV))
-    return code, it.value, rr.value
+    if k == 1 and nrhs == 1:
+        return code, int(it[0]), float(rr[0])
+    return code, it.reshape(k, nrhs), rr.reshape(k, nrhs)

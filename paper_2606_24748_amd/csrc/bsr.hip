@@ -61,7 +61,7 @@ void ensure_host_pattern(bsr_s* A) {
 // (G, U) for a matrix: G lanes per block row, U blocks per lane per step.  The
 // heuristic targets about one step per row with enough bytes in flight per wave;
 // BLKAMG_SPMV_LANES="GxU" overrides it (experiments).
-int lanes_for(const bsr_s* A) {
+int lanes_for(const bsr_s* A, int nrhs) {
   static int forced = -1;
   if (forced < 0) {
     forced = 0;
@@ -71,6 +71,7 @@ int lanes_for(const bsr_s* A) {
     }
   }
   if (forced > 0) return forced;
+  if (const int t = A->tuned[nrhs > 1 ? 1 : 0]) return t;
   const double avg = A->avg_blocks_per_row();
   const size_t vb = A->block_elems() * dtype_size(A->dtype);  // bytes per block
   int G;
@@ -124,8 +125,8 @@ __global__ void spmv_generic_kernel(int nbr, int br, int bc, int nrhs, const int
 }
 
 template <int BR, int BC, class TM, class TX, class TA>
-void spmv_fast(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s) {
-  const int G = lanes_for(A);
+void spmv_fast(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code = 0) {
+  const int G = code ? code : lanes_for(A, nrhs);
   const auto* v = static_cast<const TM*>(A->val);
   if (nrhs == 1) {
     launch_rows<BR, BC, 1, TM, TX, TA>(G, A->nbr, A->rowptr, A->colidx, v, x, EpiAxpby<TX, TA>{y, alpha, beta}, s);
@@ -135,14 +136,14 @@ void spmv_fast(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, 
 }
 
 template <class TM, class TX, class TA>
-void spmv_typed(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s) {
+void spmv_typed(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code) {
   if (A->nbr == 0) return;
   const int br = A->br, bc = A->bc;
   if (nrhs == 1 || nrhs == 8) {
-    if (br == 3 && bc == 3) return spmv_fast<3, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s);
-    if (br == 3 && bc == 6) return spmv_fast<3, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s);
-    if (br == 6 && bc == 3) return spmv_fast<6, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s);
-    if (br == 6 && bc == 6) return spmv_fast<6, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s);
+    if (br == 3 && bc == 3) return spmv_fast<3, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
+    if (br == 3 && bc == 6) return spmv_fast<3, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
+    if (br == 6 && bc == 3) return spmv_fast<6, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
+    if (br == 6 && bc == 6) return spmv_fast<6, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
   }
   const int64_t total = static_cast<int64_t>(A->nbr) * br * nrhs;
   const int grid = static_cast<int>(std::min<int64_t>((total + 255) / 256, 1 << 20));
@@ -189,22 +190,58 @@ void cast_values(const void* src, int sdt, void* dst, int ddt, size_t n, hipStre
   HIP_CHECK(hipGetLastError());
 }
 
-void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs,
-          hipStream_t s) {
+void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs, hipStream_t s,
+          int code) {
   BLK_REQUIRE(nrhs >= 1 && nrhs <= 8, BLKAMG_EINVAL, "nrhs must be in 1..8");
   if (A->nbr > 0) BLK_REQUIRE(y != nullptr, BLKAMG_EINVAL, "y is NULL");
   if (A->nnzb > 0) BLK_REQUIRE(x != nullptr, BLKAMG_EINVAL, "x is NULL");
   if (A->dtype == BLKAMG_F64 && vdt == BLKAMG_F64) {
-    spmv_typed<double, double, double>(A, alpha, static_cast<const double*>(x), beta, static_cast<double*>(y), nrhs, s);
+    spmv_typed<double, double, double>(A, alpha, static_cast<const double*>(x), beta, static_cast<double*>(y), nrhs, s,
+                                       code);
   } else if (A->dtype == BLKAMG_F32 && vdt == BLKAMG_F32) {
     spmv_typed<float, float, float>(A, static_cast<float>(alpha), static_cast<const float*>(x),
-                                    static_cast<float>(beta), static_cast<float*>(y), nrhs, s);
+                                    static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code);
   } else if (A->dtype == BLKAMG_BF16 && vdt == BLKAMG_F32) {
     spmv_typed<bf16, float, float>(A, static_cast<float>(alpha), static_cast<const float*>(x),
-                                   static_cast<float>(beta), static_cast<float*>(y), nrhs, s);
+                                   static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code);
   } else {
     fail(BLKAMG_EINVAL, "unsupported matrix/vector dtype combination");
   }
+}
+
+int autotune_lanes(bsr_s* A, int vdt, int nrhs, hipStream_t s) {
+  BLK_REQUIRE(nrhs == 1 || nrhs == 8, BLKAMG_EINVAL, "autotune supports nrhs 1 or 8");
+  if (A->nbr == 0 || A->nnzb == 0) return lanes_for(A, nrhs);
+  const size_t vs = dtype_size(vdt == BLKAMG_F64 ? BLKAMG_F64 : BLKAMG_F32);
+  DevBuf<char> x(static_cast<size_t>(A->nbc) * A->bc * nrhs * vs);
+  DevBuf<char> y(static_cast<size_t>(A->nbr) * A->br * nrhs * vs);
+  HIP_CHECK(hipMemsetAsync(x.p, 0, x.bytes(), s));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.0f;
+  try {
+    for (int code : kLaneCodes) {
+      for (int w = 0; w < 2; ++w) spmv(A, 1.0, x.p, 0.0, y.p, vdt, nrhs, s, code);
+      constexpr int kReps = 5;
+      HIP_CHECK(hipEventRecord(e0, s));
+      for (int r = 0; r < kReps; ++r) spmv(A, 1.0, x.p, 0.0, y.p, vdt, nrhs, s, code);
+      HIP_CHECK(hipEventRecord(e1, s));
+      HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (best == 0 || ms < best_ms) { best = code; best_ms = ms; }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  A->tuned[nrhs > 1 ? 1 : 0] = best;
+  return best;
 }
 
 bsr_s* transpose_of(bsr_s* A, hipStream_t s) {
@@ -353,6 +390,15 @@ int bsr_arrays(bsr_t A, const int32_t** d_rowptr, const int32_t** d_colidx, void
   if (d_rowptr) *d_rowptr = A->rowptr;
   if (d_colidx) *d_colidx = A->colidx;
   if (d_val) *d_val = A->val;
+  BLK_API_END
+}
+
+int bsr_autotune(bsr_t A, int vec_dtype, int32_t nrhs, void* stream, int32_t* code) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(A != nullptr, BLKAMG_EINVAL, "A is NULL");
+  BLK_REQUIRE(vec_dtype == BLKAMG_F64 || vec_dtype == BLKAMG_F32, BLKAMG_EINVAL, "vec_dtype must be F64 or F32");
+  const int c = autotune_lanes(A, vec_dtype, nrhs, as_stream(stream));
+  if (code) *code = c;
   BLK_API_END
 }
 

@@ -29,6 +29,7 @@ struct bsr_s {
   blk::DevBuf<int32_t> own_rowptr, own_colidx;
   blk::DevBuf<char> own_val;
   uint64_t stamp = 1;  // value-state stamp
+  int tuned[2] = {0, 0};  // autotuned SpMV lane code for 1 and for 8 right-hand sides (0 = heuristic)
   std::unique_ptr<blk::TransposeCache> tcache;
   // host copy of the pattern (filled on demand or at creation)
   std::vector<int32_t> h_rowptr, h_colidx;
@@ -51,10 +52,15 @@ void ensure_host_pattern(bsr_s* A);
 // Transpose cache of A, built if needed; values refreshed on `s` if stale.
 bsr_s* transpose_of(bsr_s* A, hipStream_t s);
 // y = alpha op(A) x + beta y
+// (code != 0 forces that lane configuration)
 void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs,
-          hipStream_t s);
-// Number of lanes cooperating on one block row.
-int lanes_for(const bsr_s* A);
+          hipStream_t s, int code = 0);
+// SpMV lane configuration (G * 8 + U) for A with nrhs right-hand sides: the
+// autotuned one if present, else a heuristic on the mean blocks per row.
+int lanes_for(const bsr_s* A, int nrhs = 1);
+// Time every compiled lane configuration of y = A x (vectors of dtype vdt, nrhs
+// columns) with device events and keep the fastest in A; returns its code.  Sync.
+int autotune_lanes(bsr_s* A, int vdt, int nrhs, hipStream_t s);
 // Structural product of two host block patterns (sorted rows, no dropping).
 void structural_product_host(int32_t nra, const std::vector<int32_t>& rpa, const std::vector<int32_t>& cia,
                              int32_t ncb, const std::vector<int32_t>& rpb, const std::vector<int32_t>& cib,

@@ -129,6 +129,9 @@ int launch_g(int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* va
 // per step.  Encoded as G * 8 + U.
 inline int lane_code(int G, int U) { return G * 8 + U; }
 
+// Every lane code launch_rows compiles.
+constexpr int kLaneCodes[] = {8 * 8 + 1, 8 * 8 + 2, 16 * 8 + 1, 16 * 8 + 2, 32 * 8 + 1, 32 * 8 + 2, 64 * 8 + 1, 64 * 8 + 2};
+
 // Launch spmv_kernel with (G, U) chosen at run time; returns the number of
 // workgroups (= number of partial sums written by a reducing epilogue).
 template <int BR, int BC, int NR, class TM, class TX, class TA, class Epi>
@@ -148,6 +151,7 @@ int launch_rows(int code, int nbr, const int32_t* rowptr, const int32_t* colidx,
     BLK_CASE(32, 1)
     BLK_CASE(32, 2)
     BLK_CASE(64, 1)
+    BLK_CASE(64, 2)
 #undef BLK_CASE
     default:
       grid = launch_g<BR, BC, NR, 64, 2, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s);

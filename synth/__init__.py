@@ -22,3 +22,4 @@ from .q1 import (  # noqa: F401
     stream_sizes,
 )
 from .random_bsr import random_bsr, random_spd_bsr, random_coo_stream  # noqa: F401
+from .batch import batch_sizes, make_batch, batch_values, batch_values_torch  # noqa: F401
