@@ -62,6 +62,14 @@ extern "C" {
 #define BLKAMG_INSERT 0
 #define BLKAMG_ADD 1
 
+/* source of lambda_hat in the smoother refresh (blkamg_opts.eig_mode) */
+#define BLKAMG_EIG_LANCZOS 0 /* k-step Lanczos per level (paper's method) */
+#define BLKAMG_EIG_MLP 1     /* learned eigenbound with growth test and Lanczos fallback */
+
+/* eigenbound network 12 -> 64 -> 64 -> 2: parameter count and deployable model size */
+#define BLKAMG_MLP_PARAMS 5122
+#define BLKAMG_MLP_MODEL 5150
+
 typedef struct bsr_s* bsr_t;
 typedef struct coo_plan_s* coo_plan_t;
 typedef struct amg_s* amg_t;
@@ -200,6 +208,9 @@ typedef struct {
   int32_t autotune_nrhs;    /* 0: heuristic SpMV lane shapes; 1 or 8: at setup, time every
                                compiled shape of each hierarchy SpMV (and of A0) for that
                                many right-hand sides and keep the fastest.  Default 0 */
+  int32_t eig_mode;         /* BLKAMG_EIG_LANCZOS (default) or BLKAMG_EIG_MLP: refreshes
+                               take lambda_hat from the model set by amg_set_eig_model
+                               (the cold setup always uses Lanczos) */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -292,6 +303,65 @@ int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* st
  * nrhs, rtol or maxit change).  Sync. */
 int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol,
               int32_t maxit, int32_t nrhs, int32_t* iters, double* relres, void* stream);
+
+/* ==========================================================================
+ * Learned eigenbound (replaces the per-level Lanczos estimate of lambda_max(D^-1 A)
+ * that sets the Chebyshev interval, paper §4.1, and the prolongator-smoothing
+ * weight, paper §2.2; Lanczos stays as fallback and as reference)
+ * ========================================================================== */
+
+/* C[m][n] = op(A) op(B) on the matrix cores (v_mfma_f32_16x16x4_f32), FP32.
+ * op(A) is m x k: A row-major [m][lda] (trans_a = 0) or [k][lda] read transposed
+ * (trans_a = 1); likewise op(B) k x n from [k][ldb] or [n][ldb].  C row-major
+ * [m][ldc] is overwritten.  Async. */
+int mlp_gemm_f32(int32_t trans_a, int32_t trans_b, int32_t m, int32_t n, int32_t k,
+                 const float* d_a, int32_t lda, const float* d_b, int32_t ldb,
+                 float* d_c, int32_t ldc, void* stream);
+/* Network forward on n standardised feature rows d_x [n][12]:
+ * H1 = relu(X W1 + b1) [n][64], H2 = relu(H1 W2 + b2) [n][64], Y = H2 W3 + b3 [n][2].
+ * d_theta: BLKAMG_MLP_PARAMS floats, W1 [12][64], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64][2], b3 [2] (row-major, in x out).  Async. */
+int mlp_forward(const float* d_theta, const float* d_x, int32_t n, float* d_h1,
+                float* d_h2, float* d_y, void* stream);
+/* Gradient of L = 1/(2n) sum (Y - T)^2 with respect to theta, from the forward
+ * results; d_t [n][2]; d_work: 130 n floats of scratch; d_grad: BLKAMG_MLP_PARAMS
+ * floats (overwritten); *d_loss (device double, may be NULL) = L.  Async. */
+int mlp_loss_grad(const float* d_theta, const float* d_x, const float* d_h1,
+                  const float* d_h2, const float* d_y, const float* d_t, int32_t n,
+                  float* d_work, float* d_grad, double* d_loss, void* stream);
+/* One Adam step (Kingma & Ba, Algorithm 1) on n_params FP32 master weights with
+ * moments d_m, d_v (start at zero); step counts from 1.  Async. */
+int mlp_adam(float* d_theta, const float* d_grad, float* d_m, float* d_v, int32_t n_params,
+             int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Network inputs of every smoothed (level, instance) pair, computed by one
+ * block-row reduction kernel per level from the current operators (block-diagonal
+ * inverses are refreshed first): d_feat [n_samples][12] FP32 (may be NULL to only
+ * count), samples level-major, instances in level order; h_level, h_inst
+ * (n_samples entries each, may be NULL) name each sample.  The twelve features are
+ * logs of the max, mean and RMS of the Gershgorin row bounds of D^-1 A, of
+ * 1 + max and 1 + mean of the off-diagonal block norms of D^-1 A, of the
+ * diagonal-block norm contrast, the mean and max blocks per row, log scalar rows,
+ * level index, block size / 6, and feature 4 minus feature 1.  Sync. */
+int amg_features(amg_t M, float* d_feat, int32_t* n_samples, int32_t* h_level,
+                 int32_t* h_inst, void* stream);
+/* Reference lambda_max(D^-1 A) per (level, instance), double[n_levels-1][n_inst]
+ * (0 where not smoothed): k steps (2..64) of Lanczos in the D inner product with
+ * full reorthogonalisation, FP64 vectors, started like the level's estimate.
+ * Uses the current block-diagonal inverses (amg_smoother_refresh or setup).  Sync. */
+int amg_judge_lambdas(amg_t M, int32_t k, double* h_lam, void* stream);
+/* Install a trained model: h_model = BLKAMG_MLP_MODEL floats, the parameters then
+ * feature mean[12], feature std[12], target mean[2], target std[2]; targets are
+ * (log lambda_max, omega).  With eig_mode BLKAMG_EIG_MLP, amg_smoother_refresh
+ * then takes lambda_hat = exp(prediction) per (level, instance), runs the smoother
+ * growth test on every level (A-norm of one smoother application to a fixed
+ * splitmix64 vector from f = 0 must not grow) and falls back to Lanczos on each
+ * level where some instance fails it.  Sync (copies the model). */
+int amg_set_eig_model(amg_t M, const float* h_model, int32_t n_floats);
+/* Outcome of the last MLP refresh: h_fallback[n_levels-1] (1 = level fell back to
+ * Lanczos), h_growth and h_omega [n_levels-1][n_inst] (growth factor of the test
+ * and predicted prolongator weight; 0 where not smoothed).  Any may be NULL. */
+int amg_eig_status(amg_t M, int32_t* h_fallback, double* h_growth, double* h_omega);
 
 #ifdef __cplusplus
 }

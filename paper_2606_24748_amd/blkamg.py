@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libblkamg.so")
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EBREAKDOWN, ENOTSPD = 0, 1, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 INSERT, ADD = 0, 1
+EIG_LANCZOS, EIG_MLP = 0, 1
+MLP_PARAMS, MLP_MODEL = 5122, 5150
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2606_24748_amd/build.py (or __graft_entry__.build())")
@@ -47,6 +49,7 @@ class Opts(C.Structure):
         ("p_dtype", C.c_int32),
         ("pcg_graph_iters", C.c_int32),
         ("autotune_nrhs", C.c_int32),
+        ("eig_mode", C.c_int32),
     ]
 
 
@@ -82,6 +85,14 @@ _SIG = {
     "amg_galerkin_recompute": (C.c_int, [_p, _p]),
     "amg_smoother_refresh": (C.c_int, [_p, _p, _p]),
     "vcycle_apply": (C.c_int, [_p, _p, _p, _i32, _p]),
+    "mlp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _i32, _i32, _p, _i32, _p, _i32, _p, _i32, _p]),
+    "mlp_forward": (C.c_int, [_p, _p, _i32, _p, _p, _p, _p]),
+    "mlp_loss_grad": (C.c_int, [_p, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p]),
+    "mlp_adam": (C.c_int, [_p, _p, _p, _p, _i32, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _p]),
+    "amg_features": (C.c_int, [_p, _p, _pi32, _p, _p, _p]),
+    "amg_judge_lambdas": (C.c_int, [_p, _i32, _p, _p]),
+    "amg_set_eig_model": (C.c_int, [_p, _p, _i32]),
+    "amg_eig_status": (C.c_int, [_p, _p, _p, _p]),
     "pcg_solve": (C.c_int, [_p, _p, _p, _p, _f64, _i32, _i32, _pi32, C.POINTER(_f64), _p]),
 }
 
@@ -404,3 +415,68 @@ def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, nrhs=1, stream=None):
     if k == 1 and nrhs == 1:
         return code, int(it[0]), float(rr[0])
     return code, it.reshape(k, nrhs), rr.reshape(k, nrhs)
+
+
+# ------------------------------------------------------------------------------
+# learned eigenbound
+# ------------------------------------------------------------------------------
+def mlp_gemm_f32(a, b, c, trans_a=False, trans_b=False, stream=None):
+    """c = op(a) op(b) for 2-D float32 device tensors (row-major, contiguous)."""
+    m = a.shape[1] if trans_a else a.shape[0]
+    k = a.shape[0] if trans_a else a.shape[1]
+    n = b.shape[0] if trans_b else b.shape[1]
+    _check(_lib.mlp_gemm_f32(int(trans_a), int(trans_b), m, n, k, _ptr(a), a.shape[1], _ptr(b), b.shape[1], _ptr(c),
+                             c.shape[1], _stream(stream)), "mlp_gemm_f32")
+
+
+def mlp_forward(theta, x, h1, h2, y, stream=None):
+    _check(_lib.mlp_forward(_ptr(theta), _ptr(x), x.shape[0], _ptr(h1), _ptr(h2), _ptr(y), _stream(stream)),
+           "mlp_forward")
+
+
+def mlp_loss_grad(theta, x, h1, h2, y, t, work, grad, loss=None, stream=None):
+    _check(_lib.mlp_loss_grad(_ptr(theta), _ptr(x), _ptr(h1), _ptr(h2), _ptr(y), _ptr(t), x.shape[0], _ptr(work),
+                              _ptr(grad), _ptr(loss), _stream(stream)), "mlp_loss_grad")
+
+
+def mlp_adam(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib.mlp_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(), int(step), float(lr), float(beta1),
+                         float(beta2), float(eps), _stream(stream)), "mlp_adam")
+
+
+def amg_features(M: Amg, stream=None):
+    """(features [n_samples][12] float32 device tensor, level[n], instance[n])."""
+    import torch
+    n = _i32()
+    _check(_lib.amg_features(M.h, None, C.byref(n), None, None, _stream(stream)), "amg_features")
+    lev = np.zeros(n.value, dtype=np.int32)
+    inst = np.zeros(n.value, dtype=np.int32)
+    feat = torch.zeros(max(n.value, 1), 12, dtype=torch.float32, device="cuda")
+    _check(_lib.amg_features(M.h, _ptr(feat), C.byref(n), lev.ctypes.data_as(_p), inst.ctypes.data_as(_p),
+                             _stream(stream)), "amg_features")
+    return feat[:n.value], lev, inst
+
+
+def amg_judge_lambdas(M: Amg, k=50, stream=None):
+    """[n_levels - 1][n_inst] reference lambda_max (k-step reorthogonalised Lanczos)."""
+    lam = np.zeros((max(M.num_levels() - 1, 0), M.num_instances()))
+    if lam.size:
+        _check(_lib.amg_judge_lambdas(M.h, int(k), lam.ctypes.data_as(_p), _stream(stream)), "amg_judge_lambdas")
+    return lam
+
+
+def amg_set_eig_model(M: Amg, model: np.ndarray):
+    model = np.ascontiguousarray(model, dtype=np.float32)
+    _check(_lib.amg_set_eig_model(M.h, model.ctypes.data_as(_p), model.size), "amg_set_eig_model")
+
+
+def amg_eig_status(M: Amg):
+    """(fallback[n_levels-1], growth[n_levels-1][n_inst], omega[n_levels-1][n_inst])."""
+    nl = max(M.num_levels() - 1, 0)
+    k = M.num_instances()
+    fb = np.zeros(nl, dtype=np.int32)
+    g = np.zeros((nl, k))
+    om = np.zeros((nl, k))
+    _check(_lib.amg_eig_status(M.h, fb.ctypes.data_as(_p), g.ctypes.data_as(_p), om.ctypes.data_as(_p)),
+           "amg_eig_status")
+    return fb, g, om

@@ -568,8 +568,18 @@ void check_flags(amg_s* M, hipStream_t s) {
 }
 
 // h_lambda: NULL (Lanczos) or [n_levels - 1][n_inst] user values.
+void mlp_refresh(amg_s* M, hipStream_t s);
+
 void smoother_refresh(amg_s* M, const double* h_lambda, hipStream_t s) {
   const int nl = static_cast<int>(M->lv.size());
+  if (!h_lambda && M->o.eig_mode == BLKAMG_EIG_MLP && M->model.p) {
+    for (int l = 0; l < nl; ++l)
+      if (M->lv[l]->n_act > 0) compute_dinv(M, *M->lv[l], s);
+    mlp_refresh(M, s);
+    for (int l = 0; l < nl; ++l) coarse_factor(M, *M->lv[l], s);
+    check_flags(M, s);
+    return;
+  }
   std::vector<DevBuf<double>> user(static_cast<size_t>(nl));
   for (int l = 0; l < nl; ++l) {
     Level& L = *M->lv[l];
@@ -587,6 +597,245 @@ void smoother_refresh(amg_s* M, const double* h_lambda, hipStream_t s) {
     coarse_factor(M, L, s);
   }
   check_flags(M, s);  // syncs the stream: the user arrays may be freed after it
+}
+
+// ---------------------------------------------------------------------------
+// Learned eigenbound: features, reference Lanczos, smoother growth test
+// ---------------------------------------------------------------------------
+// samples = (level, smoothed segment) pairs, level-major
+void map_samples(amg_s* M) {
+  const int nl = static_cast<int>(M->lv.size());
+  M->sample_base.assign(static_cast<size_t>(nl) + 1, 0);
+  for (int l = 0; l < nl; ++l) M->sample_base[l + 1] = M->sample_base[l] + M->lv[l]->n_act;
+  M->n_samples = M->sample_base[nl];
+}
+
+// features of the smoothed segments of level l into feat[0 .. n_act)[12] (needs Dinv)
+void level_features(amg_s* M, int l, float* feat, hipStream_t s) {
+  Level& L = *M->lv[l];
+  if (L.n_act == 0) return;
+  const bsr_s* A = L.A_act.get();
+  const SegGrid& g = L.lgrid;
+  if (g.nchunk > 0) {
+#define BLK_FEAT(BS, T)                                                                                    \
+  feature_stats_kernel<BS, T, T><<<g.nchunk, 256, 0, s>>>(A->rowptr, A->colidx, static_cast<const T*>(A->val), \
+                                                         reinterpret_cast<const T*>(L.dinv.p), g.lo.p, g.hi.p,  \
+                                                         M->partial.p)
+    if (M->T == BLKAMG_F64) { if (L.bs == 3) BLK_FEAT(3, double); else BLK_FEAT(6, double); }
+    else { if (L.bs == 3) BLK_FEAT(3, float); else BLK_FEAT(6, float); }
+#undef BLK_FEAT
+    HIP_CHECK(hipGetLastError());
+  }
+  feature_finish_kernel<<<(L.n_act + 63) / 64, 64, 0, s>>>(M->partial.p, g.ptr.p, L.d_act_off.p, L.n_act, L.bs, l, feat);
+  HIP_CHECK(hipGetLastError());
+}
+
+void all_features(amg_s* M, float* feat, hipStream_t s) {
+  for (size_t l = 0; l < M->lv.size(); ++l)
+    level_features(M, static_cast<int>(l), feat + static_cast<size_t>(M->sample_base[l]) * 12, s);
+}
+
+template <class TV>
+TV* lanczos_vec(Level& L, int t, size_t n) {
+  if constexpr (sizeof(TV) == 8) {
+    if (L.lz[t].n < n) L.lz[t].alloc(n);
+    return reinterpret_cast<TV*>(L.lz[t].p);
+  } else {
+    if (L.lzf[t].n < n) L.lzf[t].alloc(n);
+    return reinterpret_cast<TV*>(L.lzf[t].p);
+  }
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (alpha[0..m), beta[0..m-1)) by
+// Sturm bisection to full precision.
+double tridiag_max(const double* alpha, const double* beta, int m) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(beta[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(beta[i]) : 0.0);
+    lo = std::min(lo, alpha[i] - r);
+    hi = std::max(hi, alpha[i] + r);
+  }
+  for (int it = 0; it < 300; ++it) {
+    const double x = 0.5 * (lo + hi);
+    if (x <= lo || x >= hi) break;
+    int cnt = 0;
+    double q = alpha[0] - x;
+    cnt += q < 0;
+    for (int i = 1; i < m; ++i) {
+      q = alpha[i] - x - beta[i - 1] * beta[i - 1] / (q != 0.0 ? q : 1e-300);
+      cnt += q < 0;
+    }
+    if (cnt == m) hi = x; else lo = x;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Reference estimate of lambda_max(D^-1 A) per smoothed segment of level l: k steps
+// of Lanczos in the D inner product with full reorthogonalisation, FP64 vectors.
+template <int BS, class TM>
+std::vector<double> judge_level_bs(amg_s* M, int l, int k, hipStream_t s) {
+  Level& L = *M->lv[l];
+  const bsr_s* A = L.A_act.get();
+  const int nbr = A->nbr, ns = L.n_act;
+  const size_t n = static_cast<size_t>(nbr) * BS;
+  DevBuf<double> U(n * k), Y(n * k), wu(n), wy(n), coef(static_cast<size_t>(ns) * kMaxLanczos);
+  DevBuf<LevelScalars> jsc(static_cast<size_t>(ns));
+  HIP_CHECK(hipMemsetAsync(jsc.p, 0, jsc.bytes(), s));
+  const size_t need = static_cast<size_t>(L.lgrid.nchunk) * k;
+  if (M->partial.n < need) {
+    HIP_CHECK(hipStreamSynchronize(s));
+    M->partial.alloc(need);
+    M->epoch++;
+  }
+  const int32_t* off = L.d_act_off.p;
+  const TM* val = static_cast<const TM*>(A->val);
+  const TM* dinv = reinterpret_cast<const TM*>(L.dinv.p);
+  const int G = lanes_for(A, 1);
+  lanczos_start_kernel<BS, TM, double><<<vgrid(nbr), 256, 0, s>>>(
+      nbr, off, ns, M->o.lanczos_seed + static_cast<uint64_t>(l), val, L.diag_idx.p, wu.p, wy.p);
+  seg_reduce<1>(M, L.lgrid, wu.p, wy.p, OpLzSqrt{jsc.p, -1}, s);
+  lanczos_scale_kernel<BS, double><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, jsc.p, -1, wu.p, wy.p, U.p, Y.p);
+  HIP_CHECK(hipGetLastError());
+  for (int step = 0; step < k; ++step) {
+    double* u = U.p + static_cast<size_t>(step) * n;
+    double* y = Y.p + static_cast<size_t>(step) * n;
+    launch_rows<BS, BS, 1, TM, double, double>(G, nbr, A->rowptr, A->colidx, val, u,
+                                                EpiAxpby<double, double>{wy.p, 1.0, 0.0}, s);
+    seg_reduce<1>(M, L.lgrid, u, wy.p, OpLzAlpha{jsc.p, step}, s);
+    if (step == k - 1) break;
+    judge_orth_kernel<BS><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, jsc.p, step, y, step > 0 ? y - n : nullptr, wy.p);
+    judge_dinv_kernel<BS, TM><<<vgrid(nbr), 256, 0, s>>>(nbr, dinv, wy.p, wu.p);
+    HIP_CHECK(hipGetLastError());
+    const int kk = step + 1;
+    if (L.lgrid.nchunk > 0)
+      multi_dot_kernel<<<L.lgrid.nchunk, 256, 0, s>>>(Y.p, n, kk, wu.p, L.lgrid.lo.p, L.lgrid.hi.p, M->partial.p);
+    seg_finish_kernel<OpStoreCoef><<<ns * kk, 256, 0, s>>>(M->partial.p, L.lgrid.ptr.p, kk, OpStoreCoef{coef.p});
+    judge_reorth_kernel<<<vgrid(n), 256, 0, s>>>(n, BS, off, ns, kk, coef.p, U.p, Y.p, wu.p, wy.p);
+    HIP_CHECK(hipGetLastError());
+    seg_reduce<1>(M, L.lgrid, wu.p, wy.p, OpLzSqrt{jsc.p, step}, s);
+    lanczos_scale_kernel<BS, double><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, jsc.p, step, wu.p, wy.p, u + n, y + n);
+    HIP_CHECK(hipGetLastError());
+  }
+  std::vector<LevelScalars> h = download(jsc.p, static_cast<size_t>(ns));
+  std::vector<double> lam(static_cast<size_t>(ns));
+  for (int t = 0; t < ns; ++t) {
+    int m = std::min(k, (L.seg_off[t + 1] - L.seg_off[t]) * BS);  // no more steps than dofs
+    for (int j = 0; j + 1 < m; ++j)
+      if (!(h[t].beta[j] > 1e-14 * std::fabs(h[t].alpha[j]))) { m = j + 1; break; }
+    lam[t] = tridiag_max(h[t].alpha, h[t].beta, m);
+  }
+  return lam;
+}
+
+std::vector<double> judge_level(amg_s* M, int l, int k, hipStream_t s) {
+  Level& L = *M->lv[l];
+  if (L.n_act == 0) return {};
+  if (M->T == BLKAMG_F64) return L.bs == 3 ? judge_level_bs<3, double>(M, l, k, s) : judge_level_bs<6, double>(M, l, k, s);
+  return L.bs == 3 ? judge_level_bs<3, float>(M, l, k, s) : judge_level_bs<6, float>(M, l, k, s);
+}
+
+// A-norm growth test of the smoother of level l with its current Chebyshev
+// coefficients: e0 from splitmix64 (seed kGrowthSeed), e1 = smoother result for
+// f = 0 from x0 = e0; sc[l][seg].tmp[1] = e0.Ae0, tmp[2] = e1.Ae1.
+constexpr uint64_t kGrowthSeed = 0xC0FFEE;
+
+template <int BS, class TV>
+void growth_level_bs(amg_s* M, int l, hipStream_t s) {
+  Level& L = *M->lv[l];
+  const bsr_s* A = L.A_act.get();
+  const int nbr = A->nbr, ns = L.n_act;
+  const size_t n = static_cast<size_t>(nbr) * BS;
+  TV* e0 = lanczos_vec<TV>(L, 0, n);
+  TV* scratch = lanczos_vec<TV>(L, 1, n);
+  TV* w = lanczos_vec<TV>(L, 2, n);
+  TV* zero = lanczos_vec<TV>(L, 3, n);
+  TV* x = buf<TV>(L.x);
+  TV* r = buf<TV>(L.r);
+  TV* d = buf<TV>(L.d);
+  TV* d2 = buf<TV>(L.d2);
+  LevelScalars* sc = M->sc.p + static_cast<size_t>(l) * M->n_inst;
+  const int32_t* off = L.d_act_off.p;
+  const TV* val = static_cast<const TV*>(A->val);
+  const TV* dinv = buf<TV>(L.dinv);
+  HIP_CHECK(hipMemsetAsync(zero, 0, n * sizeof(TV), s));
+  lanczos_start_kernel<BS, TV, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, kGrowthSeed, val, L.diag_idx.p, e0, scratch);
+  HIP_CHECK(hipGetLastError());
+  const int G = lanes_for(A, 1);
+  launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
+  seg_reduce<1>(M, L.lgrid, e0, w, OpStoreTmp{sc, 1}, s);
+  {
+    EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, off, ns, 0};
+    smooth<M_INITX, 1, TV>(A, e0, e, s);
+  }
+  for (int t = 1; t < M->o.cheb_degree; ++t) {
+    const bool last = (t == M->o.cheb_degree - 1);
+    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, x, x, dinv, sc, off, ns, t - 1};
+    smooth<M_STEP, 1, TV>(A, d, e, s);
+    std::swap(d, d2);
+  }
+  launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, x, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
+  seg_reduce<1>(M, L.lgrid, x, w, OpStoreTmp{sc, 2}, s);
+}
+
+void growth_level(amg_s* M, int l, hipStream_t s) {
+  Level& L = *M->lv[l];
+  if (L.n_act == 0) return;
+  if (M->T == BLKAMG_F64) { if (L.bs == 3) growth_level_bs<3, double>(M, l, s); else growth_level_bs<6, double>(M, l, s); }
+  else { if (L.bs == 3) growth_level_bs<3, float>(M, l, s); else growth_level_bs<6, float>(M, l, s); }
+}
+
+// lambda_hat of every smoothed segment from the network: features -> standardise ->
+// forward -> lambda, omega; then the Chebyshev coefficients from them, the growth
+// test on every level, and Lanczos on every level where some segment's smoother
+// grows the A-norm.  Sync.
+void mlp_refresh(amg_s* M, hipStream_t s) {
+  BLK_REQUIRE(M->model.p != nullptr, BLKAMG_ESTATE, "eig_mode is MLP but no model was set (amg_set_eig_model)");
+  const int nl = static_cast<int>(M->lv.size());
+  const int S = M->n_samples;
+  if (M->feat.n < static_cast<size_t>(S) * 12 + 1) {
+    const size_t ns = static_cast<size_t>(std::max(S, 1));
+    M->feat.alloc(ns * 12);
+    M->fx.alloc(ns * 12);
+    M->fh1.alloc(ns * kMlpHid);
+    M->fh2.alloc(ns * kMlpHid);
+    M->fy.alloc(ns * kMlpOut);
+    M->pred_lam.alloc(ns);
+    M->pred_omega.alloc(ns);
+  }
+  all_features(M, M->feat.p, s);
+  if (S > 0) {
+    const float* stats = M->model.p + kMlpParams;
+    feature_normalize_kernel<<<(S * 12 + 255) / 256, 256, 0, s>>>(S, M->feat.p, stats, M->fx.p);
+    HIP_CHECK(hipGetLastError());
+    mlp_forward_dev(M->model.p, M->fx.p, S, M->fh1.p, M->fh2.p, M->fy.p, s);
+    predict_finish_kernel<<<(S + 255) / 256, 256, 0, s>>>(S, M->fy.p, stats + 24, M->pred_lam.p, M->pred_omega.p);
+    HIP_CHECK(hipGetLastError());
+  }
+  for (int l = 0; l < nl; ++l) {
+    if (M->lv[l]->n_act == 0) continue;
+    refresh_level_scalars(M, l, M->pred_lam.p + M->sample_base[l], s);
+    growth_level(M, l, s);
+  }
+  std::vector<LevelScalars> sc = download(M->sc.p, static_cast<size_t>(nl) * M->n_inst);
+  std::vector<double> om = download(M->pred_omega.p, static_cast<size_t>(std::max(S, 0)));
+  M->fallback.assign(static_cast<size_t>(nl), 0);
+  M->growth.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
+  M->omega.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
+  for (int l = 0; l < nl; ++l) {
+    const Level& L = *M->lv[l];
+    bool bad = false;
+    for (int t = 0; t < L.n_act; ++t) {
+      const LevelScalars& q = sc[static_cast<size_t>(l) * M->n_inst + t];
+      const double g = q.tmp[1] > 0.0 ? std::sqrt(std::max(q.tmp[2], 0.0) / q.tmp[1]) : 0.0;
+      M->growth[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = g;
+      M->omega[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = om[M->sample_base[l] + t];
+      bad = bad || !(g <= 1.0) || !(q.lam > 0.0) || !std::isfinite(q.lam);
+    }
+    if (bad) {
+      M->fallback[l] = 1;
+      refresh_level_scalars(M, l, nullptr, s);
+    }
+  }
 }
 
 void galerkin_recompute(amg_s* M, hipStream_t s) {
@@ -687,6 +936,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   BLK_REQUIRE(o.pcg_graph_iters >= 0 && o.pcg_graph_iters <= 64, BLKAMG_EINVAL, "pcg_graph_iters must be in 0..64");
   BLK_REQUIRE(o.autotune_nrhs == 0 || o.autotune_nrhs == 1 || o.autotune_nrhs == 8, BLKAMG_EINVAL,
               "autotune_nrhs must be 0, 1 or 8");
+  BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
   BLK_REQUIRE(n_inst >= 1, BLKAMG_EINVAL, "n_inst must be >= 1");
   std::vector<int32_t> row0(static_cast<size_t>(n_inst) + 1);
   if (h_row0) {
@@ -873,6 +1123,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     upload(M->d_fine_dof_off, d32);
   }
   ensure_vectors(M.get(), 1);
+  map_samples(M.get());
   smoother_refresh(M.get(), nullptr, s);
   if (o.autotune_nrhs > 0) autotune_hierarchy(M.get(), o.autotune_nrhs, s);
   HIP_CHECK(hipStreamSynchronize(s));
@@ -1115,6 +1366,7 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->p_dtype = BLKAMG_F64;
   o->pcg_graph_iters = 4;
   o->autotune_nrhs = 0;
+  o->eig_mode = BLKAMG_EIG_LANCZOS;
 }
 
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream,
@@ -1220,6 +1472,71 @@ int amg_smoother_refresh(amg_t M, const double* h_lambda, void* stream) {
         BLK_REQUIRE(h_lambda[l * M->n_inst + L.seg_inst[t]] > 0.0, BLKAMG_EINVAL, "lambda must be positive");
     }
   smoother_refresh(M, h_lambda, as_stream(stream));
+  BLK_API_END
+}
+
+int amg_features(amg_t M, float* d_feat, int32_t* n_samples, int32_t* h_level, int32_t* h_inst, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  if (n_samples) *n_samples = M->n_samples;
+  for (size_t l = 0; l < M->lv.size(); ++l)
+    for (int t = 0; t < M->lv[l]->n_act; ++t) {
+      const int k = M->sample_base[l] + t;
+      if (h_level) h_level[k] = static_cast<int32_t>(l);
+      if (h_inst) h_inst[k] = M->lv[l]->seg_inst[t];
+    }
+  if (d_feat) {
+    hipStream_t s = as_stream(stream);
+    for (auto& lp : M->lv)
+      if (lp->n_act > 0) compute_dinv(M, *lp, s);
+    all_features(M, d_feat, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  BLK_API_END
+}
+
+int amg_judge_lambdas(amg_t M, int32_t k, double* h_lam, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr && h_lam != nullptr, BLKAMG_EINVAL, "NULL argument");
+  BLK_REQUIRE(k >= 2 && k <= kMaxLanczos, BLKAMG_EINVAL, "k must be in 2..64");
+  hipStream_t s = as_stream(stream);
+  const size_t nl = M->lv.size();
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    for (int t = 0; t < M->n_inst; ++t) h_lam[l * M->n_inst + t] = 0.0;
+    const Level& L = *M->lv[l];
+    const std::vector<double> lam = judge_level(M, static_cast<int>(l), k, s);
+    for (int t = 0; t < L.n_act; ++t) h_lam[l * M->n_inst + L.seg_inst[t]] = lam[t];
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  BLK_API_END
+}
+
+int amg_set_eig_model(amg_t M, const float* h_model, int32_t n_floats) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr && h_model != nullptr, BLKAMG_EINVAL, "NULL argument");
+  BLK_REQUIRE(n_floats == kMlpModel, BLKAMG_EINVAL, "a model has BLKAMG_MLP_MODEL floats");
+  for (int j = 0; j < 12; ++j)
+    BLK_REQUIRE(h_model[kMlpParams + 12 + j] > 0.f, BLKAMG_EINVAL, "feature std must be positive");
+  BLK_REQUIRE(h_model[kMlpParams + 26] > 0.f && h_model[kMlpParams + 27] > 0.f, BLKAMG_EINVAL,
+              "target std must be positive");
+  HIP_CHECK(hipDeviceSynchronize());
+  std::vector<float> h(h_model, h_model + kMlpModel);
+  upload(M->model, h);
+  BLK_API_END
+}
+
+int amg_eig_status(amg_t M, int32_t* h_fallback, double* h_growth, double* h_omega) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  const size_t nl = M->lv.size();
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    if (h_fallback) h_fallback[l] = l < M->fallback.size() ? M->fallback[l] : 0;
+    for (int t = 0; t < M->n_inst; ++t) {
+      const size_t k = l * M->n_inst + t;
+      if (h_growth) h_growth[k] = k < M->growth.size() ? M->growth[k] : 0.0;
+      if (h_omega) h_omega[k] = k < M->omega.size() ? M->omega[k] : 0.0;
+    }
+  }
   BLK_API_END
 }
 
