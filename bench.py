@@ -49,12 +49,16 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per cube edge")
-    ap.add_argument("--variants", default="mixed,fp64", help="comma list of mixed, mixed-bf16, fp64")
+    ap.add_argument("--variants", default="mixed,mixed-mlp,fp64",
+                    help="comma list of mixed, mixed-mlp, mixed-bf16, fp64")
     ap.add_argument("--probe-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only assemble the fine operator and run the SpMV probe and the copy calibration")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve section")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-eigenbound section")
+    ap.add_argument("--learned-n", type=int, default=96, help="edge of the learned-eigenbound deployment problem")
+    ap.add_argument("--model", default=None, help="eigenbound model JSON (default: the packaged one)")
     ap.add_argument("--batch-eager", action="store_true",
                     help="also time the batched CG launched eagerly (no graph replay)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -222,6 +226,79 @@ def run_batch(args, B, torch, dev, stream):
     return res
 
 
+def run_learned(args, B, torch, dev, stream):
+    """Deployment of the learned eigenbound on Q1 elasticity at learned_n^3 elements
+    (material seed 21, redraw 1021, right-hand side seed 22): FP32 hierarchy with
+    Lanczos refresh vs FP32 hierarchy with the network refresh (growth test, Lanczos
+    fallback), plus the plain FP64 path; one step = assemble + recompute + refresh +
+    PCG to 1e-8.  lambda errors are taken against 50-step reorthogonalised Lanczos."""
+    import numpy as np
+
+    import synth
+    from paper_2606_24748_amd import train_eigmlp
+
+    model = train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL)
+    n = args.learned_n
+    mesh = synth.make_mesh(n)
+    ii, jj = synth.coo_indices(mesh)
+    vals = [synth.coo_values_torch(mesh, *synth.lame(*synth.materials(mesh.n_elem, sd)), dev) for sd in (21, 1021)]
+    b = torch.as_tensor(synth.rhs(mesh, 22), device=dev)
+    plan, HA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, ii, jj)
+    del ii, jj
+    res = {"n": n, "dofs": mesh.n_dof}
+    for name, hier, eig in (("mixed-lanczos", B.F32, B.EIG_LANCZOS), ("mixed-mlp", B.F32, B.EIG_MLP),
+                            ("fp64-lanczos", B.F64, B.EIG_LANCZOS)):
+        B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
+        o = B.blkamg_opts_default()
+        o.hier_dtype, o.p_dtype, o.eig_mode = hier, hier, eig
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
+        t_setup = time.perf_counter() - t0
+        if eig == B.EIG_MLP:
+            B.amg_set_eig_model(M, model)
+        x = torch.zeros_like(b)
+        rec = []
+        for s in range(args.warmup + args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            vi = (s + 1) % 2
+            ev[0].record(stream)
+            B.coo_assemble_blocked(plan, vals[vi], B.INSERT, HA)
+            ev[1].record(stream)
+            B.amg_galerkin_recompute(M)
+            ev[2].record(stream)
+            B.amg_smoother_refresh(M)
+            ev[3].record(stream)
+            code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000)
+            ev[4].record(stream)
+            ev[4].synchronize()
+            ph = [ev[k].elapsed_time(ev[k + 1]) for k in range(4)]
+            if s >= args.warmup:
+                rec.append({"coo_ms": ph[0], "ptap_ms": ph[1], "refresh_ms": ph[2], "pcg_ms": ph[3], "its": its,
+                            "status": code, "relres": rel})
+            log(f"[learned/{name}] step {s}: refresh {ph[2]:.2f} ms, pcg {ph[3]:.1f} ms ({its} its)")
+        med = {k: statistics.median(r[k] for r in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
+        lam = M.lambdas().tolist()
+        judge = B.amg_judge_lambdas(M, 50)[:, 0].tolist()
+        ent = {"setup_s": t_setup, "median_ms": med, "steps": rec, "lambda": lam, "lambda_judge": judge,
+               "lambda_rel_err": [a / j - 1.0 for a, j in zip(lam, judge)],
+               "refresh_plus_pcg_ms": med["refresh_ms"] + med["pcg_ms"],
+               "ptap_plus_pcg_ms": med["ptap_ms"] + med["pcg_ms"]}
+        if eig == B.EIG_MLP:
+            fb, g, om = B.amg_eig_status(M)
+            ent["fallback_levels"] = fb.tolist()
+            ent["growth"] = g[:, 0].tolist()
+            ent["omega_pred"] = om[:, 0].tolist()
+        res[name] = ent
+        del M
+        torch.cuda.synchronize()
+    res["mlp_vs_lanczos_refresh_speedup"] = (res["mixed-lanczos"]["median_ms"]["refresh_ms"] /
+                                             res["mixed-mlp"]["median_ms"]["refresh_ms"])
+    res["mixed_mlp_vs_fp64_solve_speedup"] = (res["fp64-lanczos"]["refresh_plus_pcg_ms"] /
+                                              res["mixed-mlp"]["refresh_plus_pcg_ms"])
+    return res
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.cpu_baseline_only:
@@ -271,6 +348,8 @@ def main(argv=None):
             o.hier_dtype, o.p_dtype = B.F64, B.F64
         elif var == "mixed":
             o.hier_dtype, o.p_dtype = B.F32, B.F32
+        elif var == "mixed-mlp":
+            o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, B.EIG_MLP
         elif var == "mixed-bf16":
             o.hier_dtype, o.p_dtype = B.F32, B.BF16
         else:
@@ -280,6 +359,9 @@ def main(argv=None):
         t0 = time.perf_counter()
         M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
         t_setup = time.perf_counter() - t0
+        if var == "mixed-mlp":
+            from paper_2606_24748_amd import train_eigmlp
+            B.amg_set_eig_model(M, train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL))
         nl = M.num_levels()
         lev = []
         for l in range(nl):
@@ -339,14 +421,23 @@ def main(argv=None):
             "x_norm": float(torch.linalg.norm(x)),
         }
         results[var]["_x"] = x
+        results[var]["lambdas"] = M.lambdas().tolist()
+        if var == "mixed-mlp":
+            fb, g, _ = B.amg_eig_status(M)
+            results[var]["fallback_levels"] = fb.tolist()
+            results[var]["growth"] = g[:, 0].tolist()
         del M
         torch.cuda.synchronize()
 
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
     batch = None
-    if not args.no_batch:
-        del plan, HA, vals
+    learned = None
+    del plan, HA, vals
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        learned = run_learned(args, B, torch, dev, stream)
         torch.cuda.empty_cache()
+    if not args.no_batch:
         batch = run_batch(args, B, torch, dev, stream)
     achieved, spmv_b, spmv_ms = probe["achieved_GBs"], probe["bytes_per_launch"], probe["avg_launch_ms"]
 
@@ -383,6 +474,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "variants": results,
         "batch": batch,
+        "learned": learned,
         "coo_plan_s": t_plan,
     }
     if "fp64" in results and head != "fp64":
