@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libblkamg.so")
+LIB_PATH = os.environ.get("BLKAMG_LIB") or os.path.join(_HERE, "libblkamg.so")
 
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EBREAKDOWN, ENOTSPD = 0, 1, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
