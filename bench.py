@@ -38,6 +38,30 @@ if ROOT not in sys.path:
 
 METRIC = "PCG solve s + PtAP recompute s at 128^3 elasticity; %HBM peak; mixed vs FP64"
 
+# HBM traffic of the roofline kernel (fine 3x3 FP64 bsr_spmv at 128^3) from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes, scaled by the copy-kernel calibration; valid only for
+# the kernel sources it was measured on (their SHA-256 below), else reported as null.
+# Summary and commands: profiles/bsr_spmv_fine_f64_128cube.md.
+TRAFFIC_RECORD = None
+TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_amd/csrc/bsr.hip",
+                   "paper_2606_24748_amd/csrc/common.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    rec = TRAFFIC_RECORD
+    if not rec or rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -468,7 +492,7 @@ def main(argv=None):
                                f"{len(hr['levels'])}-level SA, Chebyshev(2) V-cycle PCG to 1e-8",
                    "n": n, "dofs": mesh.n_dof, "variant": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / RL.HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / RL.HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "bsr_spmv fine 3x3 f64 (spmv_kernel<3,3,1,32,double,double,double,EpiAxpby>)",
                      "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
         "cpu_baseline": cpu,

@@ -215,7 +215,8 @@ __global__ void lanczos_orth_kernel(int nbr, const int32_t* __restrict__ off, in
   }
 }
 
-// SpMV epilogue: wy = A u - beta_{step-1, seg} * y_prev (no previous vector on step 0)
+// SpMV epilogue: wy = A u - beta_{step-1, seg} * y_prev (no previous vector on step 0);
+// one right-hand side, BR <= G: lane i < BR owns output i
 template <class TV, class TA>
 struct EpiLanczos {
   static constexpr bool kReduce = false;
@@ -227,27 +228,24 @@ struct EpiLanczos {
   int step;
   double* partial = nullptr;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ RowVals<double, BR * NR + 1> prefetch(bool active, int row) const {
-    RowVals<double, BR * NR + 1> p;
-#pragma unroll
-    for (int t = 0; t <= BR * NR; ++t) p.v[t] = 0.0;
-    if (active && step > 0) {
-      p.v[BR * NR] = sc[seg_of(off, nseg, row)].beta[step - 1];
-#pragma unroll
-      for (int t = 0; t < BR * NR; ++t) p.v[t] = static_cast<double>(y_prev[static_cast<size_t>(row) * (BR * NR) + t]);
+  __device__ __forceinline__ RowVals<double, 2> prefetch(bool active, int row) const {
+    static_assert(lane_owned<BR * NR, G>(), "Lanczos epilogue expects BR * NR <= G");
+    RowVals<double, 2> p;
+    p.v[0] = 0.0;
+    p.v[1] = 0.0;
+    const int lane = static_cast<int>(threadIdx.x) % G;
+    if (active && step > 0 && lane < BR * NR) {
+      p.v[1] = sc[seg_of(off, nseg, row)].beta[step - 1];
+      p.v[0] = static_cast<double>(y_prev[static_cast<size_t>(row) * (BR * NR) + lane]);
     }
     return p;
   }
   template <int BR, int NR, int G>
   __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR],
-                                          const RowVals<double, BR * NR + 1>& pre) const {
-    if (!active) return 0.0;
-#pragma unroll
-    for (int l = 0; l < BR * NR; ++l) {
-      if ((l % G) != lane) continue;
-      wy[static_cast<size_t>(row) * (BR * NR) + l] =
-          static_cast<TV>(static_cast<double>(s[l]) - pre.v[BR * NR] * pre.v[l]);
-    }
+                                          const RowVals<double, 2>& pre) const {
+    if (!active || lane >= BR * NR) return 0.0;
+    wy[static_cast<size_t>(row) * (BR * NR) + lane] =
+        static_cast<TV>(static_cast<double>(pick<BR * NR>(s, lane)) - pre.v[1] * pre.v[0]);
     return 0.0;
   }
 };
@@ -330,9 +328,11 @@ enum SmoothMode { M_RESID = 0, M_INITX = 1, M_STEP = 2 };
 //   RESID : r_out = f - s
 //   INITX : r = f - s ; d = Dinv r / theta ; x_out = x_in + d   (writes r, d, x_out)
 //   STEP  : r = f - s (f = current r) ; d' = c1 d_in + c2 Dinv r ; x_out = x_in + d'
-// With one right-hand side the own-row operands are loaded before the product (their
-// latency then hides behind the block loads); with several they are loaded after it,
-// which keeps the register footprint of the 6x6 x 8 case within the VGPR file.
+// One right-hand side: lane i < BR owns output i; it loads f_i, d_i, x_i, row i of
+// Dinv and the two coefficients before the product (their latency then hides behind
+// the block loads), and the residual entries reach the other owners by shuffles.
+// Eight right-hand sides: lane q < 8 owns column q of the row (all BR entries), so
+// D^-1 r stays inside the lane; its operands are loaded after the product.
 template <int MODE, class TV, class TA>
 struct EpiSmooth {
   static constexpr bool kReduce = false;
@@ -349,33 +349,36 @@ struct EpiSmooth {
   int step;
   double* partial = nullptr;
 
-  template <int BR, int NR>
-  static constexpr int pre_len() { return NR == 1 ? 3 * BR * NR + BR * BR + 2 : 1; }
+  template <int BR, int NR, int G>
+  static constexpr int pre_len() { return 3 + BR + 2; }
 
-  // own-row operand t: [0,N) f, [N,2N) d_in, [2N,3N) x_in, [3N,3N+BR*BR) Dinv, then c1, c2
-  template <int BR, int NR>
-  __device__ __forceinline__ TA operand(int row, int t) const {
-    constexpr int N = BR * NR;
-    const size_t b = static_cast<size_t>(row) * N;
-    if (t < N) return ld<TA>(f + b + t);
-    if (t < 2 * N) return MODE == M_STEP ? ld<TA>(d_in + b + t - N) : TA(0);
-    if (t < 3 * N) return MODE != M_RESID ? ld<TA>(x_in + b + t - 2 * N) : TA(0);
-    if (t < 3 * N + BR * BR) return MODE != M_RESID ? ld<TA>(dinv + static_cast<size_t>(row) * (BR * BR) + t - 3 * N) : TA(0);
-    if (MODE == M_RESID) return TA(0);
-    const LevelScalars* S = sc + (nseg > 1 ? seg_of(off, nseg, row) : 0);
-    if (t == 3 * N + BR * BR) return MODE == M_STEP ? static_cast<TA>(S->coef[1 + 2 * step]) : TA(0);
-    return MODE == M_STEP ? static_cast<TA>(S->coef[2 + 2 * step]) : static_cast<TA>(S->coef[0]);
+  __device__ __forceinline__ const LevelScalars& scal(int row) const {
+    return sc[nseg > 1 ? seg_of(off, nseg, row) : 0];
   }
 
   template <int BR, int NR, int G>
-  __device__ __forceinline__ RowVals<TA, pre_len<BR, NR>()> prefetch(bool active, int row) const {
-    RowVals<TA, pre_len<BR, NR>()> p;
+  __device__ __forceinline__ RowVals<TA, pre_len<BR, NR, G>()> prefetch(bool active, int row) const {
+    static_assert(NR == 1 && lane_owned<BR, G>(), "one right-hand side with BR <= G");
+    RowVals<TA, pre_len<BR, NR, G>()> p;
 #pragma unroll
-    for (int t = 0; t < pre_len<BR, NR>(); ++t) p.v[t] = TA(0);
-    if constexpr (NR == 1) {
-      if (active) {
+    for (int t = 0; t < pre_len<BR, NR, G>(); ++t) p.v[t] = TA(0);
+    const int lane = static_cast<int>(threadIdx.x) % G;
+    if (active && lane < BR) {
+      const size_t o = static_cast<size_t>(row) * BR + lane;
+      p.v[0] = ld<TA>(f + o);
+      if (MODE == M_STEP) p.v[1] = ld<TA>(d_in + o);
+      if (MODE != M_RESID) {
+        p.v[2] = ld<TA>(x_in + o);
+        const TV* D = dinv + static_cast<size_t>(row) * (BR * BR) + lane * BR;
 #pragma unroll
-        for (int t = 0; t < pre_len<BR, NR>(); ++t) p.v[t] = operand<BR, NR>(row, t);
+        for (int j = 0; j < BR; ++j) p.v[3 + j] = ld<TA>(D + j);
+        const LevelScalars& S = scal(row);
+        if (MODE == M_INITX) {
+          p.v[3 + BR + 1] = static_cast<TA>(S.coef[0]);
+        } else {
+          p.v[3 + BR] = static_cast<TA>(S.coef[1 + 2 * step]);
+          p.v[3 + BR + 1] = static_cast<TA>(S.coef[2 + 2 * step]);
+        }
       }
     }
     return p;
@@ -383,47 +386,56 @@ struct EpiSmooth {
 
   template <int BR, int NR, int G>
   __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR],
-                                          const RowVals<TA, pre_len<BR, NR>()>& pre) const {
-    constexpr int N = BR * NR;
+                                          const RowVals<TA, pre_len<BR, NR, G>()>& pre) const {
     if (!active) return 0.0;
-    auto get = [&](int t) -> TA {
-      if constexpr (NR == 1) return pre.v[t];
-      else return operand<BR, NR>(row, t);
-    };
-    const size_t base = static_cast<size_t>(row) * N;
-    TA r[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) r[t] = get(t) - s[t];
+    // every lane of the group takes part in the shuffles; lanes >= BR carry zeros
+    const TA r = pre.v[0] - pick<BR>(s, lane < BR ? lane : 0);
+    const size_t o = static_cast<size_t>(row) * BR + lane;
     if (MODE == M_RESID) {
-#pragma unroll
-      for (int l = 0; l < N; ++l)
-        if ((l % G) == lane) r_out[base + l] = static_cast<TV>(r[l]);
+      if (lane < BR) r_out[o] = static_cast<TV>(r);
       return 0.0;
     }
-    TA z[N];
+    TA z = TA(0);
 #pragma unroll
-    for (int i = 0; i < BR; ++i) {
-#pragma unroll
-      for (int q = 0; q < NR; ++q) z[i * NR + q] = TA(0);
-#pragma unroll
-      for (int j = 0; j < BR; ++j) {
-        const TA dij = get(3 * N + i * BR + j);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) z[i * NR + q] = fmadd(dij, r[j * NR + q], z[i * NR + q]);
-      }
-    }
-    const TA c1 = get(3 * N + BR * BR), c2 = get(3 * N + BR * BR + 1);
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      if ((l % G) != lane) continue;
-      const size_t o = base + l;
-      TA dn = c2 * z[l];
-      if (MODE == M_STEP) dn = fmadd(c1, get(N + l), dn);
-      x_out[o] = static_cast<TV>(get(2 * N + l) + dn);
-      if (r_out) r_out[o] = static_cast<TV>(r[l]);
+    for (int j = 0; j < BR; ++j) z = fmadd(pre.v[3 + j], __shfl(r, j, G), z);
+    TA dn = pre.v[3 + BR + 1] * z;
+    if (MODE == M_STEP) dn = fmadd(pre.v[3 + BR], pre.v[1], dn);
+    if (lane < BR) {
+      x_out[o] = static_cast<TV>(pre.v[2] + dn);
+      if (r_out) r_out[o] = static_cast<TV>(r);
       if (d_out) d_out[o] = static_cast<TV>(dn);
     }
     return 0.0;
+  }
+
+  template <int BR, int G>
+  __device__ __forceinline__ void apply8(bool active, int row, int lane, const TA (&s)[BR]) const {
+    if (!active || lane >= 8) return;
+    const size_t base = static_cast<size_t>(row) * (BR * 8) + lane;
+    TA r[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) r[i] = ld<TA>(f + base + i * 8) - s[i];
+    if (MODE == M_RESID) {
+#pragma unroll
+      for (int i = 0; i < BR; ++i) r_out[base + i * 8] = static_cast<TV>(r[i]);
+      return;
+    }
+    const LevelScalars& S = scal(row);
+    const TA c1 = MODE == M_STEP ? static_cast<TA>(S.coef[1 + 2 * step]) : TA(0);
+    const TA c2 = MODE == M_STEP ? static_cast<TA>(S.coef[2 + 2 * step]) : static_cast<TA>(S.coef[0]);
+    const TV* D = dinv + static_cast<size_t>(row) * (BR * BR);
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      TA z = TA(0);
+#pragma unroll
+      for (int j = 0; j < BR; ++j) z = fmadd(ld<TA>(D + i * BR + j), r[j], z);
+      const size_t o = base + i * 8;
+      TA dn = c2 * z;
+      if (MODE == M_STEP) dn = fmadd(c1, ld<TA>(d_in + o), dn);
+      x_out[o] = static_cast<TV>(ld<TA>(x_in + o) + dn);
+      if (r_out) r_out[o] = static_cast<TV>(r[i]);
+      if (d_out) d_out[o] = static_cast<TV>(dn);
+    }
   }
 };
 
@@ -720,26 +732,22 @@ struct EpiPcgW {
   const double* p;
   double* w;
   double* partial;
+  // one right-hand side, lane i < BR owns output i
   template <int BR, int NR, int G>
-  __device__ __forceinline__ RowVals<double, BR * NR> prefetch(bool active, int row) const {
-    RowVals<double, BR * NR> pv;
-#pragma unroll
-    for (int t = 0; t < BR * NR; ++t) pv.v[t] = active ? p[static_cast<size_t>(row) * (BR * NR) + t] : 0.0;
+  __device__ __forceinline__ RowVals<double, 1> prefetch(bool active, int row) const {
+    static_assert(lane_owned<BR * NR, G>(), "CG epilogue expects BR * NR <= G");
+    RowVals<double, 1> pv;
+    const int lane = static_cast<int>(threadIdx.x) % G;
+    pv.v[0] = (active && lane < BR * NR) ? p[static_cast<size_t>(row) * (BR * NR) + lane] : 0.0;
     return pv;
   }
   template <int BR, int NR, int G>
   __device__ __forceinline__ double apply(bool active, int row, int lane, const double (&s)[BR * NR],
-                                          const RowVals<double, BR * NR>& pre) const {
-    double acc = 0.0;
-    if (active) {
-#pragma unroll
-      for (int l = 0; l < BR * NR; ++l) {
-        if ((l % G) != lane) continue;
-        w[static_cast<size_t>(row) * (BR * NR) + l] = s[l];
-        acc += pre.v[l] * s[l];
-      }
-    }
-    return acc;
+                                          const RowVals<double, 1>& pre) const {
+    if (!active || lane >= BR * NR) return 0.0;
+    const double v = pick<BR * NR>(s, lane);
+    w[static_cast<size_t>(row) * (BR * NR) + lane] = v;
+    return pre.v[0] * v;
   }
 };
 

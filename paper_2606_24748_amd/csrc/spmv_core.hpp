@@ -117,11 +117,79 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
 }
 
 
+// Eight right-hand sides: G = 8 S lanes per block row, lane = (slot s, column q).
+// Slot s takes blocks k0+s, k0+s+S, ...; all eight column lanes of a slot load the same
+// block (one broadcast) and their own column of the gathered x panel (eight
+// consecutive values per block column, so a slot's loads are contiguous).  Each lane
+// accumulates BR sums of its column; the S slots are then added by an xor tree that
+// keeps the column, and lanes 0..7 (slot 0) own the BR x 8 outputs of the row, so the
+// epilogue's block-row arithmetic (D^-1 r) stays inside each lane.
+template <int BR, int BC, int G, int U, class TM, class TX, class TA, class Epi>
+__global__ __launch_bounds__(kBlock) void spmm8_kernel(int nbr, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       const TM* __restrict__ val,
+                                                       const TX* __restrict__ x, Epi epi) {
+  constexpr int NR = 8;
+  constexpr int S = G / NR;
+  constexpr int kRows = kBlock / G;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
+  const int lane = static_cast<int>(threadIdx.x) % G;
+  const int q = lane % NR, slot = lane / NR;
+  TA acc[BR];
+#pragma unroll
+  for (int i = 0; i < BR; ++i) acc[i] = TA(0);
+  const bool active = row < nbr;
+  if (active) {
+    const int k1 = rowptr[row + 1];
+    for (int kb = rowptr[row] + slot; kb < k1; kb += S * U) {
+      TM bv[U][BR * BC];
+      TA xv[U][BC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + u * S;
+        if (k < k1) {
+          const TX* xc = x + static_cast<size_t>(colidx[k]) * (BC * NR) + q;
+#pragma unroll
+          for (int j = 0; j < BC; ++j) xv[u][j] = ld<TA>(xc + j * NR);
+          const TM* b = val + static_cast<size_t>(k) * (BR * BC);
+#pragma unroll
+          for (int t = 0; t < BR * BC; ++t) bv[u][t] = b[t];
+        } else {
+#pragma unroll
+          for (int j = 0; j < BC; ++j) xv[u][j] = TA(0);
+#pragma unroll
+          for (int t = 0; t < BR * BC; ++t) bv[u][t] = TM{};
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+#pragma unroll
+          for (int j = 0; j < BC; ++j) acc[i] = fmadd(ld<TA>(&bv[u][i * BC + j]), xv[u][j], acc[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = NR; off < G; off <<= 1) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[i] += __shfl_xor(acc[i], off, G);
+  }
+  epi.template apply8<BR, G>(active, row, lane, acc);
+}
+
 template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA, class Epi>
 int launch_g(int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val, const TX* x, const Epi& epi,
              hipStream_t s) {
   const int grid = ceil_div(nbr, kBlock / G);
-  spmv_kernel<BR, BC, NR, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+  if constexpr (NR == 8) {
+    static_assert(!Epi::kReduce, "reducing epilogues take one right-hand side");
+    spmm8_kernel<BR, BC, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+  } else {
+    spmv_kernel<BR, BC, NR, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+  }
   return grid;
 }
 
@@ -174,6 +242,12 @@ struct RowVals {
   T v[N];
 };
 
+// When the BR * NR outputs of a row fit in its lane group (BR * NR <= G), lane l < BR * NR
+// owns output l: it alone loads that output's own-row operands and stores it, instead
+// of every lane of the group loading all of them.
+template <int N, int G>
+constexpr bool lane_owned() { return N <= G; }
+
 // y = alpha * (A x) + beta * y
 template <class TY, class TA>
 struct EpiAxpby {
@@ -182,29 +256,56 @@ struct EpiAxpby {
   TA alpha, beta;
   double* partial = nullptr;
   template <int BR, int NR, int G>
-  __device__ __forceinline__ RowVals<TA, BR * NR> prefetch(bool active, int row) const {
-    RowVals<TA, BR * NR> p;
+  static constexpr int pre_len() { return lane_owned<BR * NR, G>() ? 1 : BR * NR; }
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ RowVals<TA, pre_len<BR, NR, G>()> prefetch(bool active, int row) const {
+    constexpr int N = BR * NR;
+    RowVals<TA, pre_len<BR, NR, G>()> p;
 #pragma unroll
-    for (int t = 0; t < BR * NR; ++t) p.v[t] = TA(0);
-    if (active && beta != TA(0)) {
+    for (int t = 0; t < pre_len<BR, NR, G>(); ++t) p.v[t] = TA(0);
+    if (!active || beta == TA(0)) return p;
+    if constexpr (lane_owned<N, G>()) {
+      const int lane = static_cast<int>(threadIdx.x) % G;
+      if (lane < N) p.v[0] = ld<TA>(y + static_cast<size_t>(row) * N + lane);
+    } else {
 #pragma unroll
-      for (int t = 0; t < BR * NR; ++t) p.v[t] = ld<TA>(y + static_cast<size_t>(row) * (BR * NR) + t);
+      for (int t = 0; t < N; ++t) p.v[t] = ld<TA>(y + static_cast<size_t>(row) * N + t);
     }
     return p;
   }
   template <int BR, int NR, int G>
   __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&acc)[BR * NR],
-                                          const RowVals<TA, BR * NR>& pre) const {
+                                          const RowVals<TA, pre_len<BR, NR, G>()>& pre) const {
+    constexpr int N = BR * NR;
     if (!active) return 0.0;
+    if constexpr (lane_owned<N, G>()) {
+      if (lane < N) {
+        TA v = alpha * pick<N>(acc, lane);
+        if (beta != TA(0)) v = fmadd(beta, pre.v[0], v);
+        st(y + static_cast<size_t>(row) * N + lane, v);
+      }
+    } else {
 #pragma unroll
-    for (int l = 0; l < BR * NR; ++l) {
-      if ((l % G) != lane) continue;
-      const size_t o = static_cast<size_t>(row) * (BR * NR) + l;
-      TA v = alpha * acc[l];
-      if (beta != TA(0)) v = fmadd(beta, pre.v[l], v);
-      st(y + o, v);
+      for (int l = 0; l < N; ++l) {
+        if ((l % G) != lane) continue;
+        TA v = alpha * acc[l];
+        if (beta != TA(0)) v = fmadd(beta, pre.v[l], v);
+        st(y + static_cast<size_t>(row) * N + l, v);
+      }
     }
     return 0.0;
+  }
+  // eight right-hand sides, column-lane layout: lane q < 8 owns column q of the row
+  template <int BR, int G>
+  __device__ __forceinline__ void apply8(bool active, int row, int lane, const TA (&acc)[BR]) const {
+    if (!active || lane >= 8) return;
+    const size_t base = static_cast<size_t>(row) * (BR * 8) + lane;
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      TA v = alpha * acc[i];
+      if (beta != TA(0)) v = fmadd(beta, ld<TA>(y + base + i * 8), v);
+      st(y + base + i * 8, v);
+    }
   }
 };
 
