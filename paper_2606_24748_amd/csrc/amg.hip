@@ -40,6 +40,7 @@ struct Level {
   int32_t act_rows = 0;
   int n = 0, bs = 0;                   // scalar dofs, block size
   DevBuf<int32_t> d_act_off;           // block-row offsets of the smoothed segments
+  DevBuf<uint16_t> d_row_seg;          // segment of each smoothed row (several segments only)
   SegGrid lgrid;                       // Lanczos dots over the smoothed dofs
   DevBuf<char> dinv;                   // [act_rows][bs][bs] hierarchy dtype
   DevBuf<int32_t> diag_idx;
@@ -248,6 +249,13 @@ void finalize_level(amg_s* M, Level& L) {
   L.A_act = prefix_view(L.A, L.act_rows);
   std::vector<int32_t> aoff(L.seg_off.begin(), L.seg_off.begin() + L.n_act + 1);
   upload(L.d_act_off, aoff);
+  L.d_row_seg.release();
+  if (L.n_act > 1) {
+    std::vector<uint16_t> rs(static_cast<size_t>(L.act_rows));
+    for (int t = 0; t < L.n_act; ++t)
+      for (int32_t r = L.seg_off[t]; r < L.seg_off[t + 1]; ++r) rs[r] = static_cast<uint16_t>(t);
+    upload(L.d_row_seg, rs);
+  }
   std::vector<int64_t> doff;
   for (int t = 0; t <= L.n_act; ++t) doff.push_back(static_cast<int64_t>(L.seg_off[t]) * L.bs);
   build_grid(M, L.lgrid, doff, 8192, kFeatStats);
@@ -463,8 +471,7 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
   const int nbr = A->nbr;
   const TV* dinv = buf<TV>(L.dinv);
   const LevelScalars* sc = M->sc.p + static_cast<size_t>(l) * M->n_inst;
-  const int32_t* off = L.d_act_off.p;
-  const int ns = L.n_act;
+  const uint16_t* rseg = L.d_row_seg.p;
   TV* x = buf<TV>(L.x);
   TV* r = buf<TV>(L.r);
   TV* d = buf<TV>(L.d);
@@ -472,19 +479,19 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
   const int k = M->o.cheb_degree;
   // pre-smoothing from a zero guess
   TV* first = (k == 1) ? x : d;
-  if (L.bs == 3) cheb0_kernel<3, NR, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, sc, f, dinv, first);
-  else cheb0_kernel<6, NR, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, sc, f, dinv, first);
+  if (L.bs == 3) cheb0_kernel<3, NR, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, rseg, sc, f, dinv, first);
+  else cheb0_kernel<6, NR, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, rseg, sc, f, dinv, first);
   HIP_CHECK(hipGetLastError());
   for (int t = 1; t < k; ++t) {
     const bool last = (t == k - 1);
     EpiSmooth<M_STEP, TV, TV> e{t == 1 ? f : r, last ? nullptr : r, d, last ? nullptr : d2, t == 1 ? d : x, x,
-                                dinv, sc, off, ns, t - 1};
+                                dinv, sc, rseg, t - 1};
     smooth<M_STEP, NR, TV>(A, d, e, s);
     std::swap(d, d2);
   }
   // residual and restriction
   {
-    EpiSmooth<M_RESID, TV, TV> e{f, r, nullptr, nullptr, nullptr, nullptr, dinv, sc, off, ns, 0};
+    EpiSmooth<M_RESID, TV, TV> e{f, r, nullptr, nullptr, nullptr, nullptr, dinv, sc, rseg, 0};
     smooth<M_RESID, NR, TV>(A, x, e, s);
   }
   Level& C = *M->lv[l + 1];
@@ -496,12 +503,12 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
   spmv(L.P.get(), 1.0, oc, 1.0, x, M->T, NR, s);
   // post-smoothing from x
   {
-    EpiSmooth<M_INITX, TV, TV> e{f, r, nullptr, d, x, out, dinv, sc, off, ns, 0};
+    EpiSmooth<M_INITX, TV, TV> e{f, r, nullptr, d, x, out, dinv, sc, rseg, 0};
     smooth<M_INITX, NR, TV>(A, x, e, s);
   }
   for (int t = 1; t < k; ++t) {
     const bool last = (t == k - 1);
-    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, out, out, dinv, sc, off, ns, t - 1};
+    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, out, out, dinv, sc, rseg, t - 1};
     smooth<M_STEP, NR, TV>(A, d, e, s);
     std::swap(d, d2);
   }
@@ -764,12 +771,12 @@ void growth_level_bs(amg_s* M, int l, hipStream_t s) {
   launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
   seg_reduce<1>(M, L.lgrid, e0, w, OpStoreTmp{sc, 1}, s);
   {
-    EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, off, ns, 0};
+    EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, L.d_row_seg.p, 0};
     smooth<M_INITX, 1, TV>(A, e0, e, s);
   }
   for (int t = 1; t < M->o.cheb_degree; ++t) {
     const bool last = (t == M->o.cheb_degree - 1);
-    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, x, x, dinv, sc, off, ns, t - 1};
+    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, x, x, dinv, sc, L.d_row_seg.p, t - 1};
     smooth<M_STEP, 1, TV>(A, d, e, s);
     std::swap(d, d2);
   }
@@ -937,7 +944,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   BLK_REQUIRE(o.autotune_nrhs == 0 || o.autotune_nrhs == 1 || o.autotune_nrhs == 8, BLKAMG_EINVAL,
               "autotune_nrhs must be 0, 1 or 8");
   BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
-  BLK_REQUIRE(n_inst >= 1, BLKAMG_EINVAL, "n_inst must be >= 1");
+  BLK_REQUIRE(n_inst >= 1 && n_inst <= 65535, BLKAMG_EINVAL, "n_inst must be in 1..65535");
   std::vector<int32_t> row0(static_cast<size_t>(n_inst) + 1);
   if (h_row0) {
     std::copy(h_row0, h_row0 + n_inst + 1, row0.begin());

@@ -24,7 +24,15 @@ struct LevelScalars {
   double lam;                     // lambda_hat
   double coef[1 + 2 * kMaxCheb];  // 1/theta, then (c1, c2) per Chebyshev step
   double tmp[4];
+  float coef_f[1 + 2 * kMaxCheb];  // the same coefficients rounded to FP32
 };
+
+// Chebyshev coefficient t in the arithmetic type of the smoother
+template <class TA>
+__device__ __forceinline__ TA cheb_coef(const LevelScalars& S, int t) {
+  if constexpr (sizeof(TA) == 4) return S.coef_f[t];
+  else return static_cast<TA>(S.coef[t]);
+}
 
 // segment of row `row` among off[0..n] (off[0] = 0 <= row < off[n])
 __device__ __forceinline__ int seg_of(const int32_t* __restrict__ off, int n, int row) {
@@ -298,19 +306,21 @@ __global__ void lanczos_finish_kernel(LevelScalars* sc, int nseg, int k, const d
     S->coef[2 + 2 * (t - 1)] = 2.0 * rho1 / delta;
     rho = rho1;
   }
+  for (int t = 0; t < 2 * degree - 1; ++t) S->coef_f[t] = static_cast<float>(S->coef[t]);
 }
 
 // ---------------------------------------------------------------------------
 // Chebyshev / point-block Jacobi (paper §4.1 pbjacobi inside Saad's Chebyshev)
 // ---------------------------------------------------------------------------
 
-// d = Dinv f / theta_seg (zero-guess start), NR right-hand sides
+// d = Dinv f / theta_seg (zero-guess start), NR right-hand sides; row_seg (NULL for
+// one segment) gives the segment of each row
 template <int BS, int NR, class TV>
-__global__ void cheb0_kernel(int nbr, const int32_t* __restrict__ off, int nseg, const LevelScalars* __restrict__ sc,
+__global__ void cheb0_kernel(int nbr, const uint16_t* __restrict__ row_seg, const LevelScalars* __restrict__ sc,
                              const TV* __restrict__ f, const TV* __restrict__ dinv, TV* __restrict__ out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nbr) return;
-  const TV it = static_cast<TV>(sc[nseg > 1 ? seg_of(off, nseg, r) : 0].coef[0]);
+  const TV it = cheb_coef<TV>(sc[row_seg ? row_seg[r] : 0], 0);
   TV fv[BS * NR];
   for (int t = 0; t < BS * NR; ++t) fv[t] = f[static_cast<size_t>(r) * BS * NR + t];
   const TV* D = dinv + static_cast<size_t>(r) * BS * BS;
@@ -344,41 +354,51 @@ struct EpiSmooth {
   TV* x_out;
   const TV* dinv;
   const LevelScalars* sc;
-  const int32_t* off;
-  int nseg;
+  const uint16_t* row_seg;  // segment of each row, NULL for one segment
   int step;
   double* partial = nullptr;
 
   template <int BR, int NR, int G>
-  static constexpr int pre_len() { return 3 + BR + 2; }
+  static constexpr int pre_len() { return 3 + BR; }
 
-  __device__ __forceinline__ const LevelScalars& scal(int row) const {
-    return sc[nseg > 1 ? seg_of(off, nseg, row) : 0];
-  }
+  __device__ __forceinline__ const LevelScalars& scal(int row) const { return sc[row_seg ? row_seg[row] : 0]; }
 
+  // own-row operands of one right-hand side, all in the arithmetic type (the
+  // coefficients come pre-rounded), so nothing has to be converted, and waited for,
+  // before the product
   template <int BR, int NR, int G>
-  __device__ __forceinline__ RowVals<TA, pre_len<BR, NR, G>()> prefetch(bool active, int row) const {
+  struct Pre {
+    RowVals<TA, 3 + BR> a;
+    TA c1, c2;
+  };
+
+  // The loads are unconditional (lanes >= BR and rows past the end read valid
+  // addresses of the same row / row 0 and their values are never stored), so no
+  // branch separates them from the product's loads.
+  template <int BR, int NR, int G>
+  __device__ __forceinline__ Pre<BR, NR, G> prefetch(bool active, int row) const {
     static_assert(NR == 1 && lane_owned<BR, G>(), "one right-hand side with BR <= G");
-    RowVals<TA, pre_len<BR, NR, G>()> p;
+    Pre<BR, NR, G> p;
 #pragma unroll
-    for (int t = 0; t < pre_len<BR, NR, G>(); ++t) p.v[t] = TA(0);
-    const int lane = static_cast<int>(threadIdx.x) % G;
-    if (active && lane < BR) {
-      const size_t o = static_cast<size_t>(row) * BR + lane;
-      p.v[0] = ld<TA>(f + o);
-      if (MODE == M_STEP) p.v[1] = ld<TA>(d_in + o);
-      if (MODE != M_RESID) {
-        p.v[2] = ld<TA>(x_in + o);
-        const TV* D = dinv + static_cast<size_t>(row) * (BR * BR) + lane * BR;
+    for (int t = 0; t < 3 + BR; ++t) p.a.v[t] = TA(0);
+    p.c1 = TA(0);
+    p.c2 = TA(0);
+    const int lane = min(static_cast<int>(threadIdx.x) % G, BR - 1);
+    const int rr = active ? row : 0;
+    const size_t o = static_cast<size_t>(rr) * BR + lane;
+    p.a.v[0] = ld<TA>(f + o);
+    if (MODE == M_STEP) p.a.v[1] = ld<TA>(d_in + o);
+    if (MODE != M_RESID) {
+      p.a.v[2] = ld<TA>(x_in + o);
+      const TV* D = dinv + static_cast<size_t>(rr) * (BR * BR) + lane * BR;
 #pragma unroll
-        for (int j = 0; j < BR; ++j) p.v[3 + j] = ld<TA>(D + j);
-        const LevelScalars& S = scal(row);
-        if (MODE == M_INITX) {
-          p.v[3 + BR + 1] = static_cast<TA>(S.coef[0]);
-        } else {
-          p.v[3 + BR] = static_cast<TA>(S.coef[1 + 2 * step]);
-          p.v[3 + BR + 1] = static_cast<TA>(S.coef[2 + 2 * step]);
-        }
+      for (int j = 0; j < BR; ++j) p.a.v[3 + j] = ld<TA>(D + j);
+      const LevelScalars& S = scal(rr);
+      if (MODE == M_INITX) {
+        p.c2 = cheb_coef<TA>(S, 0);
+      } else {
+        p.c1 = cheb_coef<TA>(S, 1 + 2 * step);
+        p.c2 = cheb_coef<TA>(S, 2 + 2 * step);
       }
     }
     return p;
@@ -386,10 +406,10 @@ struct EpiSmooth {
 
   template <int BR, int NR, int G>
   __device__ __forceinline__ double apply(bool active, int row, int lane, const TA (&s)[BR * NR],
-                                          const RowVals<TA, pre_len<BR, NR, G>()>& pre) const {
+                                          const Pre<BR, NR, G>& pre) const {
     if (!active) return 0.0;
     // every lane of the group takes part in the shuffles; lanes >= BR carry zeros
-    const TA r = pre.v[0] - pick<BR>(s, lane < BR ? lane : 0);
+    const TA r = pre.a.v[0] - pick<BR>(s, lane < BR ? lane : 0);
     const size_t o = static_cast<size_t>(row) * BR + lane;
     if (MODE == M_RESID) {
       if (lane < BR) r_out[o] = static_cast<TV>(r);
@@ -397,11 +417,11 @@ struct EpiSmooth {
     }
     TA z = TA(0);
 #pragma unroll
-    for (int j = 0; j < BR; ++j) z = fmadd(pre.v[3 + j], __shfl(r, j, G), z);
-    TA dn = pre.v[3 + BR + 1] * z;
-    if (MODE == M_STEP) dn = fmadd(pre.v[3 + BR], pre.v[1], dn);
+    for (int j = 0; j < BR; ++j) z = fmadd(pre.a.v[3 + j], __shfl(r, j, G), z);
+    TA dn = pre.c2 * z;
+    if (MODE == M_STEP) dn = fmadd(pre.c1, pre.a.v[1], dn);
     if (lane < BR) {
-      x_out[o] = static_cast<TV>(pre.v[2] + dn);
+      x_out[o] = static_cast<TV>(pre.a.v[2] + dn);
       if (r_out) r_out[o] = static_cast<TV>(r);
       if (d_out) d_out[o] = static_cast<TV>(dn);
     }
@@ -421,8 +441,8 @@ struct EpiSmooth {
       return;
     }
     const LevelScalars& S = scal(row);
-    const TA c1 = MODE == M_STEP ? static_cast<TA>(S.coef[1 + 2 * step]) : TA(0);
-    const TA c2 = MODE == M_STEP ? static_cast<TA>(S.coef[2 + 2 * step]) : static_cast<TA>(S.coef[0]);
+    const TA c1 = MODE == M_STEP ? cheb_coef<TA>(S, 1 + 2 * step) : TA(0);
+    const TA c2 = MODE == M_STEP ? cheb_coef<TA>(S, 2 + 2 * step) : cheb_coef<TA>(S, 0);
     const TV* D = dinv + static_cast<size_t>(row) * (BR * BR);
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
@@ -737,8 +757,8 @@ struct EpiPcgW {
   __device__ __forceinline__ RowVals<double, 1> prefetch(bool active, int row) const {
     static_assert(lane_owned<BR * NR, G>(), "CG epilogue expects BR * NR <= G");
     RowVals<double, 1> pv;
-    const int lane = static_cast<int>(threadIdx.x) % G;
-    pv.v[0] = (active && lane < BR * NR) ? p[static_cast<size_t>(row) * (BR * NR) + lane] : 0.0;
+    const int lane = min(static_cast<int>(threadIdx.x) % G, BR * NR - 1);
+    pv.v[0] = p[static_cast<size_t>(active ? row : 0) * (BR * NR) + lane];  // unconditional, see EpiSmooth
     return pv;
   }
   template <int BR, int NR, int G>

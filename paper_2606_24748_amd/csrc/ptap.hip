@@ -39,6 +39,7 @@ struct PtapPlan {
   int64_t ap_nslots = 0;
   DevBuf<int32_t> ap_slot_row0, c_slot_row0;  // row of the first block of each workgroup
   DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
+  int ap_cap = 0, c_cap = 0;                   // LDS capacity (entries of X rows) of a workgroup
   bool ap_vec = true, c_vec = true;
   // symmetric mode: only blocks with column >= row are computed (upper list), each
   // off-diagonal one is also stored transposed at its mirror position
@@ -338,12 +339,17 @@ __global__ __launch_bounds__(kBlock) void rap_cols_kernel(int64_t nslots, const 
 // in the order given by `perm` (sorted by contribution count at symbolic time, so the
 // lanes of a wave run loops of similar length).  For every entry k of those rows of
 // the first operand X (A or R), LDS holds ystart[k] = the start of the Y row it
-// multiplies (P row a_ci[k], or AP row r_ci[k]); when they fit, the X blocks of the
-// rows are staged in LDS too (one coalesced copy).  Y blocks are read with 16-byte
-// (FP64) or 8-byte (FP32) vector loads when VEC is set.
+// multiplies (P row a_ci[k], or AP row r_ci[k]); in the A P pass the X blocks of the
+// rows are staged in LDS too (one coalesced copy).  The LDS is sized at symbolic time
+// to the largest workgroup (`cap` entries), so small blocks (FP32) leave room for
+// more resident workgroups.  Y blocks are read with 16-byte (FP64) or 8-byte (FP32)
+// vector loads when VEC is set.
 constexpr int kMaxR = 48;
-constexpr int kLdsEntries = 2048;
-constexpr int kLdsXBytes = 45056;
+constexpr int kLdsBytes = 65536;  // per workgroup
+
+inline size_t ptap_lds_bytes(int cap, int xbytes) {
+  return ((static_cast<size_t>(cap) * 4 + 15) & ~static_cast<size_t>(15)) + static_cast<size_t>(cap) * xbytes;
+}
 
 template <class T, bool VEC, int N>
 __device__ __forceinline__ void load_y(const T* __restrict__ p, T (&v)[N]) {
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
                                                             const int32_t* __restrict__ pp, const CT* __restrict__ codes,
                                                             int shift, void* __restrict__ out,
                                                             const int32_t* __restrict__ out_idx,
-                                                            const int32_t* __restrict__ mirror) {
+                                                            const int32_t* __restrict__ mirror, int cap) {
   // kIsAP: X = A (BR x BR), Y = P (BR x BC), out AP (BR x BC) in TA
   // else : X = R (BC x BR), Y = AP (BR x BC), out C (BC x BC) in the type of A
   constexpr int XR = kIsAP ? BR : BC;  // rows of an X block
@@ -387,9 +393,9 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   constexpr int XB = XR * XC;
   constexpr int OR = XR;               // rows of an output block
   // only the AP pass stages X (A rows: ~27 blocks per row); R rows are too long
-  constexpr int kXCap = kIsAP ? kLdsXBytes / (XB * static_cast<int>(sizeof(TX))) : 1;
-  __shared__ int32_t ystart[kLdsEntries];
-  __shared__ TX xs[kXCap * XB];
+  extern __shared__ __align__(16) unsigned char ptap_lds[];
+  int32_t* ystart = reinterpret_cast<int32_t*>(ptap_lds);
+  TX* xs = reinterpret_cast<TX*>(ptap_lds + ((cap * 4 + 15) & ~15));
   const int w = xcd_logical_block(blockIdx.x, gridDim.x);
   const int64_t s_begin = static_cast<int64_t>(w) * kBlock;
   const int row0 = slot_row0[w];
@@ -397,8 +403,8 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   const int nr = row1 - row0 + 1;
   const int kbase = x_rp[row0];
   const int nk = x_rp[row1 + 1] - kbase;
-  const bool staged = nr <= kMaxR && nk <= kLdsEntries;
-  const bool xstaged = kIsAP && staged && nk <= kXCap;
+  const bool staged = nr <= kMaxR && nk <= cap;
+  const bool xstaged = kIsAP && staged;
   if (staged) {
     for (int t = threadIdx.x; t < nk; t += kBlock) ystart[t] = y_rp[x_ci[kbase + t]];
   }
@@ -497,11 +503,12 @@ void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap,
   // P blocks (BR*BC values) can be read with 2-element vector loads when the block
   // size is even and the array is aligned for it
   const bool vec = pl.ap_vec && (BR * BC) % 2 == 0 && aligned(P->val, 2 * sizeof(TP)) && sizeof(TP) >= 4;
+  const size_t lds = ptap_lds_bytes(pl.ap_cap, BR * BR * static_cast<int>(sizeof(TA_)));
 #define BLK_APK(V)                                                                                                   \
-  pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, 0, s>>>(                                        \
+  pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, lds, s>>>(                                      \
       ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
       static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_pairs.ptr.p,                                             \
-      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr)
+      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr, pl.ap_cap)
   if (vec) BLK_APK(true); else BLK_APK(false);
 #undef BLK_APK
 }
@@ -512,11 +519,12 @@ void launch_rap_pairs(const PtapPlan& pl, const bsr_s* R, const bsr_s* C, const 
   const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
   if (grid == 0) return;
   const int32_t* orp = pl.sym ? pl.c_up_rp.p : C->rowptr;
+  const size_t lds = ptap_lds_bytes(pl.c_cap, 0);
 #define BLK_RAPK(V)                                                                                                  \
-  pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V><<<grid, kBlock, 0, s>>>(                                        \
+  pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V><<<grid, kBlock, lds, s>>>(                                      \
       ns, C->nbr, pl.c_slot_row0.p, pl.c_perm.p, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, \
       ap, orp, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val,           \
-      pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr)
+      pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr, pl.c_cap)
   if (pl.c_vec) BLK_RAPK(true); else BLK_RAPK(false);
 #undef BLK_RAPK
 }
@@ -807,8 +815,22 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, orp, oci, true, plan->c_pairs);
     if (!plan->c_pairs.width) plan->sym = false;  // the searching kernel computes every block
     plan->ap_nslots = static_cast<int64_t>(apci.size());
-    upload(plan->ap_slot_row0, first_rows(aprp, kBlock));
-    upload(plan->c_slot_row0, first_rows(orp, kBlock));
+    const std::vector<int32_t> ap_w = first_rows(aprp, kBlock), c_w = first_rows(orp, kBlock);
+    upload(plan->ap_slot_row0, ap_w);
+    upload(plan->c_slot_row0, c_w);
+    // LDS capacity: the largest X extent of a workgroup that stages, within kLdsBytes
+    auto cap_of = [](const std::vector<int32_t>& w, const std::vector<int32_t>& xrp, int nrows, size_t per) {
+      int cap = 0;
+      for (size_t g = 0; g + 1 < w.size(); ++g) {
+        const int r0 = w[g], r1 = std::min(nrows - 1, w[g + 1]);
+        if (r1 - r0 + 1 > kMaxR) continue;
+        cap = std::max(cap, xrp[r1 + 1] - xrp[r0]);
+      }
+      const int lim = static_cast<int>((kLdsBytes - 16) / per);
+      return std::max(1, std::min(cap, lim));
+    };
+    plan->ap_cap = cap_of(ap_w, A->h_rowptr, A->nbr, 4 + static_cast<size_t>(A->br) * A->br * dtype_size(A->dtype));
+    plan->c_cap = cap_of(c_w, R->h_rowptr, R->nbr, 4);
     // tuning switches (experiments): BLKAMG_PTAP_TUNE="ap_sort,c_sort,ap_novec,c_novec"
     const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
     const std::string tn = tune ? tune : "ap_sort";

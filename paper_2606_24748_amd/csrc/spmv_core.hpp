@@ -48,13 +48,11 @@ __device__ __forceinline__ void block_fma(const TM* __restrict__ b, const TA (&x
 // step and issues all their loads before the multiply-adds, so a wave keeps
 // U * 64 blocks of loads in flight.
 template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA>
-__device__ __forceinline__ void row_product(const int32_t* __restrict__ rowptr,
-                                            const int32_t* __restrict__ colidx,
+__device__ __forceinline__ void row_product(const int32_t* __restrict__ colidx,
                                             const TM* __restrict__ val, const TX* __restrict__ x,
-                                            int row, int lane, TA (&acc)[BR * NR]) {
+                                            int k0, int k1, int lane, TA (&acc)[BR * NR]) {
 #pragma unroll
   for (int t = 0; t < BR * NR; ++t) acc[t] = TA(0);
-  const int k0 = rowptr[row], k1 = rowptr[row + 1];
   for (int kb = k0 + lane; kb < k1; kb += G * U) {
     TM bv[U][BR * BC];
     TA xv[U][BC * NR];
@@ -99,11 +97,17 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
   const int lane = static_cast<int>(threadIdx.x) % G;
   TA acc[BR * NR];
   const bool active = row < nbr;
-  // the epilogue's own-row operands are loaded before the product so that their
-  // latency overlaps the block loads instead of following the row reduction
+  // the row's extent is loaded first and the epilogue's own-row operands right after
+  // it, before the product: loads complete in issue order, so waiting for the extent
+  // does not wait for the operands, whose latency then overlaps the block loads
+  int k0 = 0, k1 = 0;
+  if (active) {
+    k0 = rowptr[row];
+    k1 = rowptr[row + 1];
+  }
   const auto pre = epi.template prefetch<BR, NR, G>(active, row);
   if (active) {
-    row_product<BR, BC, NR, G, U, TM, TX, TA>(rowptr, colidx, val, x, row, lane, acc);
+    row_product<BR, BC, NR, G, U, TM, TX, TA>(colidx, val, x, k0, k1, lane, acc);
   } else {
 #pragma unroll
     for (int z = 0; z < BR * NR; ++z) acc[z] = TA(0);
@@ -117,47 +121,49 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
 }
 
 
-// Eight right-hand sides: G = 8 S lanes per block row, lane = (slot s, column q).
-// Slot s takes blocks k0+s, k0+s+S, ...; all eight column lanes of a slot load the same
-// block (one broadcast) and their own column of the gathered x panel (eight
-// consecutive values per block column, so a slot's loads are contiguous).  Each lane
-// accumulates BR sums of its column; the S slots are then added by an xor tree that
-// keeps the column, and lanes 0..7 (slot 0) own the BR x 8 outputs of the row, so the
-// epilogue's block-row arithmetic (D^-1 r) stays inside each lane.
+// Eight right-hand sides, G lanes per block row, one block per lane and step (as
+// with one right-hand side, so a wave's block loads cover one contiguous stretch).
+// Each lane multiplies its block with the whole 8-column panel of x (contiguous) into
+// BR x 8 partial sums kept column by column, v[q * BR + i].  The G lanes are then
+// added by an xor tree down to 8 lanes, and the last three levels are a
+// reduce-scatter: at offset 4, 2, 1 a lane keeps the half of the columns selected by
+// its own lane bit and adds the other lane's copy of that half, so lane q ends with
+// the BR sums of column q (BR * 8 * 7 / 8 shuffles instead of BR * 8 * 3).  Lanes
+// 0..7 then own the row's outputs, column by column, so the epilogue's block-row
+// arithmetic (D^-1 r) stays inside a lane.
 template <int BR, int BC, int G, int U, class TM, class TX, class TA, class Epi>
 __global__ __launch_bounds__(kBlock) void spmm8_kernel(int nbr, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ colidx,
                                                        const TM* __restrict__ val,
                                                        const TX* __restrict__ x, Epi epi) {
   constexpr int NR = 8;
-  constexpr int S = G / NR;
+  static_assert(G >= NR, "eight right-hand sides need G >= 8");
   constexpr int kRows = kBlock / G;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
   const int lane = static_cast<int>(threadIdx.x) % G;
-  const int q = lane % NR, slot = lane / NR;
-  TA acc[BR];
+  TA v[NR * BR];  // v[q * BR + i]: row i of the block row, column q
 #pragma unroll
-  for (int i = 0; i < BR; ++i) acc[i] = TA(0);
+  for (int t = 0; t < NR * BR; ++t) v[t] = TA(0);
   const bool active = row < nbr;
   if (active) {
     const int k1 = rowptr[row + 1];
-    for (int kb = rowptr[row] + slot; kb < k1; kb += S * U) {
+    for (int kb = rowptr[row] + lane; kb < k1; kb += G * U) {
       TM bv[U][BR * BC];
-      TA xv[U][BC];
+      TA xv[U][BC * NR];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = kb + u * S;
+        const int k = kb + u * G;
         if (k < k1) {
-          const TX* xc = x + static_cast<size_t>(colidx[k]) * (BC * NR) + q;
+          const TX* xc = x + static_cast<size_t>(colidx[k]) * (BC * NR);
 #pragma unroll
-          for (int j = 0; j < BC; ++j) xv[u][j] = ld<TA>(xc + j * NR);
+          for (int t = 0; t < BC * NR; ++t) xv[u][t] = ld<TA>(xc + t);
           const TM* b = val + static_cast<size_t>(k) * (BR * BC);
 #pragma unroll
           for (int t = 0; t < BR * BC; ++t) bv[u][t] = b[t];
         } else {
 #pragma unroll
-          for (int j = 0; j < BC; ++j) xv[u][j] = TA(0);
+          for (int t = 0; t < BC * NR; ++t) xv[u][t] = TA(0);
 #pragma unroll
           for (int t = 0; t < BR * BC; ++t) bv[u][t] = TM{};
         }
@@ -167,15 +173,44 @@ __global__ __launch_bounds__(kBlock) void spmm8_kernel(int nbr, const int32_t* _
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
 #pragma unroll
-          for (int j = 0; j < BC; ++j) acc[i] = fmadd(ld<TA>(&bv[u][i * BC + j]), xv[u][j], acc[i]);
+          for (int j = 0; j < BC; ++j) {
+            const TA a = ld<TA>(&bv[u][i * BC + j]);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) v[q * BR + i] = fmadd(a, xv[u][j * NR + q], v[q * BR + i]);
+          }
         }
       }
     }
   }
+  // full sums down to 8 lanes
 #pragma unroll
-  for (int off = NR; off < G; off <<= 1) {
+  for (int off = G / 2; off >= NR; off >>= 1) {
 #pragma unroll
-    for (int i = 0; i < BR; ++i) acc[i] += __shfl_xor(acc[i], off, G);
+    for (int t = 0; t < NR * BR; ++t) v[t] += __shfl_xor(v[t], off, G);
+  }
+  // reduce-scatter over the columns: offsets 4, 2, 1 halve the columns a lane keeps
+  constexpr int H4 = 4 * BR, H2 = 2 * BR, H1 = BR;
+  const bool b4 = (lane & 4) != 0, b2 = (lane & 2) != 0, b1 = (lane & 1) != 0;
+  TA w4[H4];
+#pragma unroll
+  for (int t = 0; t < H4; ++t) {
+    const TA send = b4 ? v[t] : v[H4 + t];
+    const TA keep = b4 ? v[H4 + t] : v[t];
+    w4[t] = keep + __shfl_xor(send, 4, G);
+  }
+  TA w2[H2];
+#pragma unroll
+  for (int t = 0; t < H2; ++t) {
+    const TA send = b2 ? w4[t] : w4[H2 + t];
+    const TA keep = b2 ? w4[H2 + t] : w4[t];
+    w2[t] = keep + __shfl_xor(send, 2, G);
+  }
+  TA acc[BR];
+#pragma unroll
+  for (int t = 0; t < H1; ++t) {
+    const TA send = b1 ? w2[t] : w2[H1 + t];
+    const TA keep = b1 ? w2[H1 + t] : w2[t];
+    acc[t] = keep + __shfl_xor(send, 1, G);
   }
   epi.template apply8<BR, G>(active, row, lane, acc);
 }
@@ -265,8 +300,8 @@ struct EpiAxpby {
     for (int t = 0; t < pre_len<BR, NR, G>(); ++t) p.v[t] = TA(0);
     if (!active || beta == TA(0)) return p;
     if constexpr (lane_owned<N, G>()) {
-      const int lane = static_cast<int>(threadIdx.x) % G;
-      if (lane < N) p.v[0] = ld<TA>(y + static_cast<size_t>(row) * N + lane);
+      const int lane = min(static_cast<int>(threadIdx.x) % G, N - 1);
+      p.v[0] = ld<TA>(y + static_cast<size_t>(row) * N + lane);
     } else {
 #pragma unroll
       for (int t = 0; t < N; ++t) p.v[t] = ld<TA>(y + static_cast<size_t>(row) * N + t);
