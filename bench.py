@@ -85,6 +85,8 @@ def parse_args(argv=None):
                     help="only assemble the fine operator and run the SpMV probe and the copy calibration")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-eigenbound section")
+    ap.add_argument("--only-section", choices=("learned", "batch"), default=None,
+                    help="run only that section and print its result (profiling runs)")
     ap.add_argument("--learned-n", type=int, default=96, help="edge of the learned-eigenbound deployment problem")
     ap.add_argument("--model", default=None, help="eigenbound model JSON (default: the packaged one)")
     ap.add_argument("--batch-eager", action="store_true",
@@ -346,6 +348,11 @@ def main(argv=None):
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.only_section:
+        stream = torch.cuda.current_stream()
+        run = run_learned if args.only_section == "learned" else run_batch
+        print(json.dumps({"section": args.only_section, "result": run(args, B, torch, dev, stream)}))
+        return 0
     n = args.n
     t_all = time.perf_counter()
     mesh = synth.make_mesh(n)

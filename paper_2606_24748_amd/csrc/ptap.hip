@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void rap_cols_kernel(int64_t nslots, const 
 // more resident workgroups.  Y blocks are read with 16-byte (FP64) or 8-byte (FP32)
 // vector loads when VEC is set.
 constexpr int kMaxR = 48;
-constexpr int kLdsBytes = 65536;  // per workgroup
+constexpr int kLdsBytes = 49152;  // per workgroup
 
 inline size_t ptap_lds_bytes(int cap, int xbytes) {
   return ((static_cast<size_t>(cap) * 4 + 15) & ~static_cast<size_t>(15)) + static_cast<size_t>(cap) * xbytes;
@@ -405,20 +405,57 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   const int nk = x_rp[row1 + 1] - kbase;
   const bool staged = nr <= kMaxR && nk <= cap;
   const bool xstaged = kIsAP && staged;
+  // the output and X row pointers of the workgroup's rows, so a lane finds its row and
+  // the row's X extent in LDS instead of by a chain of global loads
+  __shared__ int32_t orp_s[kMaxR + 1], xrp_s[kMaxR + 1];
+  const bool rows_staged = nr <= kMaxR;
+  if (rows_staged && threadIdx.x <= static_cast<unsigned>(nr)) {
+    orp_s[threadIdx.x] = o_rp[row0 + threadIdx.x];
+    xrp_s[threadIdx.x] = x_rp[row0 + threadIdx.x];
+  }
+  // staging: each thread issues kSU independent loads before storing them, so a
+  // workgroup's start costs a few memory latencies rather than one per element
+  constexpr int kSU = 8;
   if (staged) {
-    for (int t = threadIdx.x; t < nk; t += kBlock) ystart[t] = y_rp[x_ci[kbase + t]];
+    for (int t0 = threadIdx.x; t0 < nk; t0 += kBlock * kSU) {
+      int c[kSU];
+#pragma unroll
+      for (int u = 0; u < kSU; ++u) c[u] = t0 + u * kBlock < nk ? x_ci[kbase + t0 + u * kBlock] : 0;
+      int ys[kSU];
+#pragma unroll
+      for (int u = 0; u < kSU; ++u) ys[u] = t0 + u * kBlock < nk ? y_rp[c[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kSU; ++u)
+        if (t0 + u * kBlock < nk) ystart[t0 + u * kBlock] = ys[u];
+    }
   }
   if (xstaged) {
     const TX* src = x_v + static_cast<size_t>(kbase) * XB;
-    for (int t = threadIdx.x; t < nk * XB; t += kBlock) xs[t] = src[t];
+    const int total = nk * XB;
+    for (int t0 = threadIdx.x; t0 < total; t0 += kBlock * kSU) {
+      TX v[kSU];
+#pragma unroll
+      for (int u = 0; u < kSU; ++u) v[u] = t0 + u * kBlock < total ? src[t0 + u * kBlock] : TX{};
+#pragma unroll
+      for (int u = 0; u < kSU; ++u)
+        if (t0 + u * kBlock < total) xs[t0 + u * kBlock] = v[u];
+    }
   }
   __syncthreads();
   const int64_t lim = nslots - s_begin;
   if (static_cast<int64_t>(threadIdx.x) >= lim) return;
   const int64_t sidx = s_begin + perm[s_begin + threadIdx.x];
   int row = row0;
-  while (o_rp[row + 1] <= sidx) ++row;
-  const int k0 = x_rp[row];
+  int k0;
+  if (rows_staged) {
+    int r = 0;
+    while (orp_s[r + 1] <= sidx) ++r;
+    row = row0 + r;
+    k0 = xrp_s[r];
+  } else {
+    while (o_rp[row + 1] <= sidx) ++row;
+    k0 = x_rp[row];
+  }
   const uint32_t mask = (1u << shift) - 1u;
   TA acc[OR * BC];
 #pragma unroll
@@ -430,7 +467,10 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   // whose A blocks come from LDS, gains nothing in FP32 and loses in FP64 (more VGPRs),
   // so it keeps one.  Large blocks keep one to stay within the VGPR file.
   constexpr int kYBytes = BR * BC * static_cast<int>(sizeof(TA));
-  constexpr int PU = (kIsAP && sizeof(TA) == 8) || kYBytes > 144 ? 1 : (kYBytes > 72 ? 2 : 4);
+#ifndef BLK_AP_PU_F64
+#define BLK_AP_PU_F64 2
+#endif
+  constexpr int PU = (kIsAP && sizeof(TA) == 8) ? BLK_AP_PU_F64 : (kYBytes > 144 ? 1 : (kYBytes > 72 ? 2 : 4));
   auto contrib = [&](const TX* xb, const TY (&yraw)[BR * BC]) {
 #pragma unroll
     for (int r = 0; r < OR; ++r) {
@@ -818,13 +858,21 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     const std::vector<int32_t> ap_w = first_rows(aprp, kBlock), c_w = first_rows(orp, kBlock);
     upload(plan->ap_slot_row0, ap_w);
     upload(plan->c_slot_row0, c_w);
-    // LDS capacity: the largest X extent of a workgroup that stages, within kLdsBytes
+    // LDS capacity: the X extent that 99.5% of the workgroups fit in (the rest read
+    // from global memory), within kLdsBytes; a larger allocation for a few outliers
+    // would cost resident workgroups everywhere (measured for FP64 A P at 128^3)
     auto cap_of = [](const std::vector<int32_t>& w, const std::vector<int32_t>& xrp, int nrows, size_t per) {
-      int cap = 0;
+      std::vector<int32_t> nk;
       for (size_t g = 0; g + 1 < w.size(); ++g) {
         const int r0 = w[g], r1 = std::min(nrows - 1, w[g + 1]);
         if (r1 - r0 + 1 > kMaxR) continue;
-        cap = std::max(cap, xrp[r1 + 1] - xrp[r0]);
+        nk.push_back(xrp[r1 + 1] - xrp[r0]);
+      }
+      int cap = 1;
+      if (!nk.empty()) {
+        const size_t q = std::min(nk.size() - 1, (nk.size() * 995) / 1000);
+        std::nth_element(nk.begin(), nk.begin() + q, nk.end());
+        cap = nk[q];
       }
       const int lim = static_cast<int>((kLdsBytes - 16) / per);
       return std::max(1, std::min(cap, lim));
