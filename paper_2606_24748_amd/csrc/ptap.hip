@@ -346,6 +346,11 @@ __global__ __launch_bounds__(kBlock) void rap_cols_kernel(int64_t nslots, const 
 // vector loads when VEC is set.
 constexpr int kMaxR = 48;
 constexpr int kLdsBytes = 49152;  // per workgroup
+#ifndef BLK_AP_XSTAGE_F64
+#define BLK_AP_XSTAGE_F64 1
+#endif
+template <bool kIsAP, class TX>
+constexpr bool kStageX = kIsAP && (sizeof(TX) == 4 || BLK_AP_XSTAGE_F64);
 
 inline size_t ptap_lds_bytes(int cap, int xbytes) {
   return ((static_cast<size_t>(cap) * 4 + 15) & ~static_cast<size_t>(15)) + static_cast<size_t>(cap) * xbytes;
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   const int kbase = x_rp[row0];
   const int nk = x_rp[row1 + 1] - kbase;
   const bool staged = nr <= kMaxR && nk <= cap;
-  const bool xstaged = kIsAP && staged;
+  const bool xstaged = kStageX<kIsAP, TX> && staged;
   // the output and X row pointers of the workgroup's rows, so a lane finds its row and
   // the row's X extent in LDS instead of by a chain of global loads
   __shared__ int32_t orp_s[kMaxR + 1], xrp_s[kMaxR + 1];
@@ -470,7 +475,20 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
 #ifndef BLK_AP_PU_F64
 #define BLK_AP_PU_F64 2
 #endif
-  constexpr int PU = (kIsAP && sizeof(TA) == 8) ? BLK_AP_PU_F64 : (kYBytes > 144 ? 1 : (kYBytes > 72 ? 2 : 4));
+#ifndef BLK_RAP_PU_F64
+#define BLK_RAP_PU_F64 2
+#endif
+#ifndef BLK_AP_PU_F32
+#define BLK_AP_PU_F32 4
+#endif
+#ifndef BLK_RAP_PU_F32
+#define BLK_RAP_PU_F32 4
+#endif
+  constexpr int PU = (kYBytes == 144 && kIsAP) ? BLK_AP_PU_F64
+                     : (kYBytes == 144 && !kIsAP) ? BLK_RAP_PU_F64
+                     : (kYBytes == 72 && kIsAP) ? BLK_AP_PU_F32
+                     : (kYBytes == 72 && !kIsAP) ? BLK_RAP_PU_F32
+                     : (kYBytes > 144 ? 1 : (kYBytes > 72 ? 2 : 4));
   auto contrib = [&](const TX* xb, const TY (&yraw)[BR * BC]) {
 #pragma unroll
     for (int r = 0; r < OR; ++r) {
@@ -482,30 +500,67 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
       }
     }
   };
-  auto locate = [&](int e, int& k, int& q) {
-    const uint32_t code = codes[e];
-    k = k0 + static_cast<int>(code >> shift);
-    const int ys = staged ? ystart[k - kbase] : y_rp[x_ci[k]];
-    q = ys + static_cast<int>(code & mask);
+  // The walk is instantiated separately for staged and unstaged workgroups, so the
+  // reads of the staged tables compile to LDS instructions: through a pointer that may
+  // address either memory they would become flat accesses, which occupy the same
+  // vector-memory pipeline as the Y gathers.
+  auto walk = [&](auto ys_staged, auto x_staged) {
+    constexpr bool YS = decltype(ys_staged)::value;
+    constexpr bool XS = decltype(x_staged)::value;
+    auto xblock = [&](int k) -> const TX* {
+      if constexpr (XS) return xs + (k - kbase) * XB;
+      else return x_v + static_cast<size_t>(k) * XB;
+    };
+    auto place = [&](uint32_t code, int& k, int& q) {
+      k = k0 + static_cast<int>(code >> shift);
+      int ys;
+      if constexpr (YS) ys = ystart[k - kbase];
+      else ys = y_rp[x_ci[k]];
+      q = ys + static_cast<int>(code & mask);
+    };
+    int e = e0;
+    if (e + PU <= e1) {
+      uint32_t cn[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) cn[u] = codes[e + u];
+      for (; e + PU <= e1; e += PU) {
+        int k[PU], q[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) place(cn[u], k[u], q[u]);
+        TY yraw[PU][BR * BC];
+        TX xraw[PU][XB];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) load_y<TY, VEC>(y_v + static_cast<size_t>(q[u]) * (BR * BC), yraw[u]);
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          const TX* xb = xblock(k[u]);
+#pragma unroll
+          for (int t = 0; t < XB; ++t) xraw[u][t] = xb[t];
+        }
+        // the next step's codes, clamped to this slot's list (always a valid address)
+#pragma unroll
+        for (int u = 0; u < PU; ++u) cn[u] = codes[min(e + PU + u, e1 - 1)];
+        // every load of the step is issued before the first multiply-add: without the
+        // barrier the scheduler interleaves them to save registers, leaving only a
+        // few gathers in flight per wave
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PU; ++u) contrib(xraw[u], yraw[u]);
+      }
+    }
+    for (; e < e1; ++e) {
+      int k, q;
+      place(codes[e], k, q);
+      TY yraw[BR * BC];
+      load_y<TY, VEC>(y_v + static_cast<size_t>(q) * (BR * BC), yraw);
+      contrib(xblock(k), yraw);
+    }
   };
-  int e = e0;
-  for (; e + PU <= e1; e += PU) {
-    int k[PU], q[PU];
-#pragma unroll
-    for (int u = 0; u < PU; ++u) locate(e + u, k[u], q[u]);
-    TY yraw[PU][BR * BC];
-#pragma unroll
-    for (int u = 0; u < PU; ++u) load_y<TY, VEC>(y_v + static_cast<size_t>(q[u]) * (BR * BC), yraw[u]);
-#pragma unroll
-    for (int u = 0; u < PU; ++u)
-      contrib(xstaged ? xs + (k[u] - kbase) * XB : x_v + static_cast<size_t>(k[u]) * XB, yraw[u]);
-  }
-  for (; e < e1; ++e) {
-    int k, q;
-    locate(e, k, q);
-    TY yraw[BR * BC];
-    load_y<TY, VEC>(y_v + static_cast<size_t>(q) * (BR * BC), yraw);
-    contrib(xstaged ? xs + (k - kbase) * XB : x_v + static_cast<size_t>(k) * XB, yraw);
+  if (staged) {
+    if constexpr (kStageX<kIsAP, TX>) walk(std::true_type{}, std::true_type{});
+    else walk(std::true_type{}, std::false_type{});
+  } else {
+    walk(std::false_type{}, std::false_type{});
   }
   if constexpr (kIsAP) {
     TA* o = static_cast<TA*>(out) + static_cast<size_t>(sidx) * (OR * BC);
@@ -543,7 +598,7 @@ void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap,
   // P blocks (BR*BC values) can be read with 2-element vector loads when the block
   // size is even and the array is aligned for it
   const bool vec = pl.ap_vec && (BR * BC) % 2 == 0 && aligned(P->val, 2 * sizeof(TP)) && sizeof(TP) >= 4;
-  const size_t lds = ptap_lds_bytes(pl.ap_cap, BR * BR * static_cast<int>(sizeof(TA_)));
+  const size_t lds = ptap_lds_bytes(pl.ap_cap, kStageX<true, TA_> ? BR * BR * static_cast<int>(sizeof(TA_)) : 0);
 #define BLK_APK(V)                                                                                                   \
   pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, lds, s>>>(                                      \
       ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
