@@ -40,6 +40,7 @@ struct PtapPlan {
   DevBuf<int32_t> ap_slot_row0, c_slot_row0;  // row of the first block of each workgroup
   DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
   int ap_cap = 0, c_cap = 0;                   // LDS capacity (entries of X rows) of a workgroup
+  int ap_nl = 1, c_nl = 1;                     // lanes per output block (1 or 3)
   bool ap_vec = true, c_vec = true;
   // symmetric mode: only blocks with column >= row are computed (upper list), each
   // off-diagonal one is also stored transposed at its mirror position
@@ -150,199 +151,15 @@ __global__ __launch_bounds__(kBlock) void rap_kernel(int ncoarse, const int32_t*
   }
 }
 
-// pass 1 with pair lists: lane per AP block, no searching.
-template <int BR, int BC, int G, class TA_, class TP, class TA, class CT>
-__global__ __launch_bounds__(kBlock) void ap_pairs_kernel(int nrows, const int32_t* __restrict__ a_rp,
-                                                          const int32_t* __restrict__ a_ci, const TA_* __restrict__ a_v,
-                                                          const int32_t* __restrict__ p_rp, const TP* __restrict__ p_v,
-                                                          const int32_t* __restrict__ ap_rp,
-                                                          const int32_t* __restrict__ pp, const CT* __restrict__ codes,
-                                                          int shift, TA* __restrict__ ap_v) {
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
-  const int lane = static_cast<int>(threadIdx.x) % G;
-  if (row >= nrows) return;
-  const int k0 = a_rp[row];
-  const uint32_t mask = (1u << shift) - 1u;
-  for (int sidx = ap_rp[row] + lane; sidx < ap_rp[row + 1]; sidx += G) {
-    TA acc[BR * BC];
-#pragma unroll
-    for (int t = 0; t < BR * BC; ++t) acc[t] = TA(0);
-    const int e1 = pp[sidx + 1];
-    for (int e = pp[sidx]; e < e1; ++e) {
-      const uint32_t c = codes[e];
-      const int k = k0 + static_cast<int>(c >> shift);
-      const int q = p_rp[a_ci[k]] + static_cast<int>(c & mask);
-      const TA_* ab = a_v + static_cast<size_t>(k) * (BR * BR);
-      const TP* pb = p_v + static_cast<size_t>(q) * (BR * BC);
-      TA pv[BR * BC];
-#pragma unroll
-      for (int t = 0; t < BR * BC; ++t) pv[t] = ld<TA>(pb + t);
-#pragma unroll
-      for (int r = 0; r < BR; ++r) {
-#pragma unroll
-        for (int m = 0; m < BR; ++m) {
-          const TA av = ld<TA>(ab + r * BR + m);
-#pragma unroll
-          for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(av, pv[m * BC + cc], acc[r * BC + cc]);
-        }
-      }
-    }
-    TA* o = ap_v + static_cast<size_t>(sidx) * (BR * BC);
-#pragma unroll
-    for (int t = 0; t < BR * BC; ++t) o[t] = acc[t];
-  }
-}
-
-// pass 2 with pair lists: lane per C block.
-template <int BR, int BC, int G, class TR, class TA, class TC, class CT>
-__global__ __launch_bounds__(kBlock) void rap_pairs_kernel(int ncoarse, const int32_t* __restrict__ r_rp,
-                                                           const int32_t* __restrict__ r_ci, const TR* __restrict__ r_v,
-                                                           const int32_t* __restrict__ ap_rp, const TA* __restrict__ ap_v,
-                                                           const int32_t* __restrict__ c_rp,
-                                                           const int32_t* __restrict__ pp, const CT* __restrict__ codes,
-                                                           int shift, TC* __restrict__ c_v) {
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int row = lb * (kBlock / G) + static_cast<int>(threadIdx.x) / G;
-  const int lane = static_cast<int>(threadIdx.x) % G;
-  if (row >= ncoarse) return;
-  const int t0 = r_rp[row];
-  const uint32_t mask = (1u << shift) - 1u;
-  for (int sidx = c_rp[row] + lane; sidx < c_rp[row + 1]; sidx += G) {
-    TA acc[BC * BC];
-#pragma unroll
-    for (int t = 0; t < BC * BC; ++t) acc[t] = TA(0);
-    const int e1 = pp[sidx + 1];
-    for (int e = pp[sidx]; e < e1; ++e) {
-      const uint32_t c = codes[e];
-      const int t = t0 + static_cast<int>(c >> shift);
-      const int q = ap_rp[r_ci[t]] + static_cast<int>(c & mask);
-      const TR* rb = r_v + static_cast<size_t>(t) * (BC * BR);
-      const TA* apb = ap_v + static_cast<size_t>(q) * (BR * BC);
-      TA apv[BR * BC];
-#pragma unroll
-      for (int z = 0; z < BR * BC; ++z) apv[z] = apb[z];
-#pragma unroll
-      for (int r = 0; r < BC; ++r) {
-#pragma unroll
-        for (int m = 0; m < BR; ++m) {
-          const TA rv = ld<TA>(rb + r * BR + m);
-#pragma unroll
-          for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(rv, apv[m * BC + cc], acc[r * BC + cc]);
-        }
-      }
-    }
-    TC* o = c_v + static_cast<size_t>(sidx) * (BC * BC);
-#pragma unroll
-    for (int z = 0; z < BC * BC; ++z) st(o + z, acc[z]);
-  }
-}
-
-// Column-lane mapping: NC lanes per output block, lane c owns output column c
-// (BR values for AP, NC values for C), so the NC lanes of a block read each
-// contributing P / AP block as one contiguous stretch and share the A / R block.
-// A workgroup covers kSlots consecutive output blocks; slot_row0[w] is the row of its
-// first block (rows of the following blocks are found by scanning forward).
-template <int NC>
-struct ColMap {
-  static constexpr int kSlots = kBlock / NC;  // 42 for NC = 6
-};
-
-template <int BR, int NC, class TA_, class TP, class TA, class CT>
-__global__ __launch_bounds__(kBlock) void ap_cols_kernel(int64_t nslots, const int32_t* __restrict__ slot_row0,
-                                                         const int32_t* __restrict__ a_rp,
-                                                         const int32_t* __restrict__ a_ci, const TA_* __restrict__ a_v,
-                                                         const int32_t* __restrict__ p_rp, const TP* __restrict__ p_v,
-                                                         const int32_t* __restrict__ ap_rp,
-                                                         const int32_t* __restrict__ pp, const CT* __restrict__ codes,
-                                                         int shift, TA* __restrict__ ap_v) {
-  constexpr int kS = ColMap<NC>::kSlots;
-  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tid = static_cast<int>(threadIdx.x);
-  if (tid >= kS * NC) return;
-  const int64_t sidx = static_cast<int64_t>(w) * kS + tid / NC;
-  const int c = tid % NC;
-  if (sidx >= nslots) return;
-  int row = slot_row0[w];
-  while (ap_rp[row + 1] <= sidx) ++row;
-  const int k0 = a_rp[row];
-  const uint32_t mask = (1u << shift) - 1u;
-  TA acc[BR];
-#pragma unroll
-  for (int r = 0; r < BR; ++r) acc[r] = TA(0);
-  const int e1 = pp[sidx + 1];
-  for (int e = pp[sidx]; e < e1; ++e) {
-    const uint32_t code = codes[e];
-    const int k = k0 + static_cast<int>(code >> shift);
-    const int q = p_rp[a_ci[k]] + static_cast<int>(code & mask);
-    const TA_* ab = a_v + static_cast<size_t>(k) * (BR * BR);
-    const TP* pb = p_v + static_cast<size_t>(q) * (BR * NC) + c;
-    TA pc[BR];
-#pragma unroll
-    for (int m = 0; m < BR; ++m) pc[m] = ld<TA>(pb + m * NC);
-#pragma unroll
-    for (int r = 0; r < BR; ++r) {
-#pragma unroll
-      for (int m = 0; m < BR; ++m) acc[r] = fmadd(ld<TA>(ab + r * BR + m), pc[m], acc[r]);
-    }
-  }
-  TA* o = ap_v + static_cast<size_t>(sidx) * (BR * NC) + c;
-#pragma unroll
-  for (int r = 0; r < BR; ++r) o[r * NC] = acc[r];
-}
-
-template <int BR, int NC, class TR, class TA, class TC, class CT>
-__global__ __launch_bounds__(kBlock) void rap_cols_kernel(int64_t nslots, const int32_t* __restrict__ slot_row0,
-                                                          const int32_t* __restrict__ r_rp,
-                                                          const int32_t* __restrict__ r_ci, const TR* __restrict__ r_v,
-                                                          const int32_t* __restrict__ ap_rp, const TA* __restrict__ ap_v,
-                                                          const int32_t* __restrict__ c_rp,
-                                                          const int32_t* __restrict__ pp, const CT* __restrict__ codes,
-                                                          int shift, TC* __restrict__ c_v) {
-  constexpr int kS = ColMap<NC>::kSlots;
-  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tid = static_cast<int>(threadIdx.x);
-  if (tid >= kS * NC) return;
-  const int64_t sidx = static_cast<int64_t>(w) * kS + tid / NC;
-  const int c = tid % NC;
-  if (sidx >= nslots) return;
-  int row = slot_row0[w];
-  while (c_rp[row + 1] <= sidx) ++row;
-  const int t0 = r_rp[row];
-  const uint32_t mask = (1u << shift) - 1u;
-  TA acc[NC];
-#pragma unroll
-  for (int r = 0; r < NC; ++r) acc[r] = TA(0);
-  const int e1 = pp[sidx + 1];
-  for (int e = pp[sidx]; e < e1; ++e) {
-    const uint32_t code = codes[e];
-    const int t = t0 + static_cast<int>(code >> shift);
-    const int q = ap_rp[r_ci[t]] + static_cast<int>(code & mask);
-    const TR* rb = r_v + static_cast<size_t>(t) * (NC * BR);
-    const TA* apb = ap_v + static_cast<size_t>(q) * (BR * NC) + c;
-    TA ac[BR];
-#pragma unroll
-    for (int m = 0; m < BR; ++m) ac[m] = apb[m * NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
-#pragma unroll
-      for (int m = 0; m < BR; ++m) acc[r] = fmadd(ld<TA>(rb + r * BR + m), ac[m], acc[r]);
-    }
-  }
-  TC* o = c_v + static_cast<size_t>(sidx) * (NC * NC) + c;
-#pragma unroll
-  for (int r = 0; r < NC; ++r) st(o + r * NC, acc[r]);
-}
-
-// Lane per output block.  A workgroup takes kBlock consecutive output blocks, which
-// belong to rows row0..row1 (row1 = first row of the next workgroup), and walks them
-// in the order given by `perm` (sorted by contribution count at symbolic time, so the
-// lanes of a wave run loops of similar length).  For every entry k of those rows of
-// the first operand X (A or R), LDS holds ystart[k] = the start of the Y row it
-// multiplies (P row a_ci[k], or AP row r_ci[k]); in the A P pass the X blocks of the
-// rows are staged in LDS too (one coalesced copy).  The LDS is sized at symbolic time
-// to the largest workgroup (`cap` entries), so small blocks (FP32) leave room for
-// more resident workgroups.  Y blocks are read with 16-byte (FP64) or 8-byte (FP32)
+// NL lanes per output block (1 or 3).  A workgroup takes kBlock / NL consecutive output
+// blocks, which belong to rows row0..row1 (row1 = first row of the next workgroup), and
+// walks them in the order given by `perm` (sorted by contribution count at symbolic
+// time, so the lanes of a wave run loops of similar length).  For every entry k of
+// those rows of the first operand X (A or R), LDS holds ystart[k] = the start of the Y
+// row it multiplies (P row a_ci[k], or AP row r_ci[k]); in the A P pass the X blocks of
+// the rows are staged in LDS too (one coalesced copy).  The LDS is sized at symbolic
+// time from the workgroups' extents (`cap` entries), so small blocks (FP32) leave room
+// for more resident workgroups.  Y blocks are read with 16-byte (FP64) or 8-byte (FP32)
 // vector loads when VEC is set.
 constexpr int kMaxR = 48;
 constexpr int kLdsBytes = 49152;  // per workgroup
@@ -380,7 +197,20 @@ __device__ __forceinline__ void load_y(const T* __restrict__ p, T (&v)[N]) {
   }
 }
 
-template <int BR, int BC, class TX, class TY, class TA, class CT, bool kIsAP, bool VEC>
+// The CW values of columns c0..c0+CW-1 of each of the R rows of a row-major block with
+// BC columns (all of it when CW == BC).
+template <class T, bool VEC, int R, int BC, int CW>
+__device__ __forceinline__ void load_ycols(const T* __restrict__ p, int c0, T (&v)[R * CW]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T row[CW];
+    load_y<T, VEC>(p + r * BC + c0, row);
+#pragma unroll
+    for (int c = 0; c < CW; ++c) v[r * CW + c] = row[c];
+  }
+}
+
+template <int BR, int BC, class TX, class TY, class TA, class CT, bool kIsAP, bool VEC, int NL>
 __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int nrows, const int32_t* __restrict__ slot_row0,
                                                             const uint8_t* __restrict__ perm,
                                                             const int32_t* __restrict__ x_rp,
@@ -397,12 +227,19 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   constexpr int XC = BR;               // cols of an X block
   constexpr int XB = XR * XC;
   constexpr int OR = XR;               // rows of an output block
+  // NL lanes per output block; lane m owns its columns m*CW .. m*CW+CW-1 and reads only
+  // those columns of every contributing Y block, so one load instruction of a wave
+  // covers whole Y rows of a few blocks (a few cache lines) instead of one 16-byte piece
+  // of 64 different blocks.  Every lane of the block reads the whole X block.
+  static_assert(BC % NL == 0, "lanes must split the columns evenly");
+  constexpr int CW = BC / NL;
+  constexpr int SPW = kBlock / NL;     // output blocks per workgroup
   // only the AP pass stages X (A rows: ~27 blocks per row); R rows are too long
   extern __shared__ __align__(16) unsigned char ptap_lds[];
   int32_t* ystart = reinterpret_cast<int32_t*>(ptap_lds);
   TX* xs = reinterpret_cast<TX*>(ptap_lds + ((cap * 4 + 15) & ~15));
   const int w = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int64_t s_begin = static_cast<int64_t>(w) * kBlock;
+  const int64_t s_begin = static_cast<int64_t>(w) * SPW;
   const int row0 = slot_row0[w];
   const int row1 = min(nrows - 1, slot_row0[w + 1]);
   const int nr = row1 - row0 + 1;
@@ -447,9 +284,11 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
     }
   }
   __syncthreads();
-  const int64_t lim = nslots - s_begin;
-  if (static_cast<int64_t>(threadIdx.x) >= lim) return;
-  const int64_t sidx = s_begin + perm[s_begin + threadIdx.x];
+  const int slot = static_cast<int>(threadIdx.x) / NL;
+  const int lm = static_cast<int>(threadIdx.x) % NL;
+  if (slot >= SPW || s_begin + slot >= nslots) return;
+  const int64_t sidx = s_begin + perm[s_begin + slot];
+  const int c0 = lm * CW;
   int row = row0;
   int k0;
   if (rows_staged) {
@@ -462,16 +301,20 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
     k0 = x_rp[row];
   }
   const uint32_t mask = (1u << shift) - 1u;
-  TA acc[OR * BC];
+  TA acc[OR * CW];
 #pragma unroll
-  for (int t = 0; t < OR * BC; ++t) acc[t] = TA(0);
+  for (int t = 0; t < OR * CW; ++t) acc[t] = TA(0);
   const int e0 = pp[sidx], e1 = pp[sidx + 1];
-  // PU contributions per step: their codes, Y-row starts and Y blocks are all loaded
-  // before the multiply-adds, so each lane keeps PU gathers in flight.  Measured at
-  // 128^3: 2-4 in flight shortens the R AP pass (FP64 7.6 -> 5.2 ms); the A P pass,
-  // whose A blocks come from LDS, gains nothing in FP32 and loses in FP64 (more VGPRs),
-  // so it keeps one.  Large blocks keep one to stay within the VGPR file.
+  // PU contributions per step: their Y blocks (and X blocks read from global memory)
+  // are all loaded before the multiply-adds, so each lane keeps PU gathers in flight;
+  // depths measured at 128^3.  Large blocks keep one to stay within the VGPR file.
   constexpr int kYBytes = BR * BC * static_cast<int>(sizeof(TA));
+#ifndef BLK_PU_SPLIT_AP
+#define BLK_PU_SPLIT_AP 4
+#endif
+#ifndef BLK_PU_SPLIT_RAP
+#define BLK_PU_SPLIT_RAP 2
+#endif
 #ifndef BLK_AP_PU_F64
 #define BLK_AP_PU_F64 2
 #endif
@@ -484,19 +327,20 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
 #ifndef BLK_RAP_PU_F32
 #define BLK_RAP_PU_F32 4
 #endif
-  constexpr int PU = (kYBytes == 144 && kIsAP) ? BLK_AP_PU_F64
+  constexpr int PU_STAGED = NL > 1 ? (kIsAP ? BLK_PU_SPLIT_AP : BLK_PU_SPLIT_RAP)
+                     : (kYBytes == 144 && kIsAP) ? BLK_AP_PU_F64
                      : (kYBytes == 144 && !kIsAP) ? BLK_RAP_PU_F64
                      : (kYBytes == 72 && kIsAP) ? BLK_AP_PU_F32
                      : (kYBytes == 72 && !kIsAP) ? BLK_RAP_PU_F32
                      : (kYBytes > 144 ? 1 : (kYBytes > 72 ? 2 : 4));
-  auto contrib = [&](const TX* xb, const TY (&yraw)[BR * BC]) {
+  auto contrib = [&](const TX* xb, const TY (&yraw)[BR * CW]) {
 #pragma unroll
     for (int r = 0; r < OR; ++r) {
 #pragma unroll
       for (int m = 0; m < XC; ++m) {
         const TA xv = ld<TA>(xb + r * XC + m);
 #pragma unroll
-        for (int cc = 0; cc < BC; ++cc) acc[r * BC + cc] = fmadd(xv, ld<TA>(&yraw[m * BC + cc]), acc[r * BC + cc]);
+        for (int cc = 0; cc < CW; ++cc) acc[r * CW + cc] = fmadd(xv, ld<TA>(&yraw[m * CW + cc]), acc[r * CW + cc]);
       }
     }
   };
@@ -507,6 +351,9 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   auto walk = [&](auto ys_staged, auto x_staged) {
     constexpr bool YS = decltype(ys_staged)::value;
     constexpr bool XS = decltype(x_staged)::value;
+    // workgroups too large for the LDS tables are rare; one pair per step keeps their
+    // instantiation from raising the kernel's register count
+    constexpr int PU = YS ? PU_STAGED : 1;
     auto xblock = [&](int k) -> const TX* {
       if constexpr (XS) return xs + (k - kbase) * XB;
       else return x_v + static_cast<size_t>(k) * XB;
@@ -527,17 +374,20 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
         int k[PU], q[PU];
 #pragma unroll
         for (int u = 0; u < PU; ++u) place(cn[u], k[u], q[u]);
-        TY yraw[PU][BR * BC];
-        TX xraw[PU][XB];
+        TY yraw[PU][BR * CW];
+        TX xraw[XS ? 1 : PU][XB];  // X blocks from global memory are loaded with the Y blocks
 #pragma unroll
-        for (int u = 0; u < PU; ++u) load_y<TY, VEC>(y_v + static_cast<size_t>(q[u]) * (BR * BC), yraw[u]);
+        for (int u = 0; u < PU; ++u)
+          load_ycols<TY, VEC, BR, BC, CW>(y_v + static_cast<size_t>(q[u]) * (BR * BC), c0, yraw[u]);
+        if constexpr (!XS) {
 #pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          const TX* xb = xblock(k[u]);
+          for (int u = 0; u < PU; ++u) {
+            const TX* xb = xblock(k[u]);
 #pragma unroll
-          for (int t = 0; t < XB; ++t) xraw[u][t] = xb[t];
+            for (int t = 0; t < XB; ++t) xraw[u][t] = xb[t];
+          }
         }
-        // the next step's codes, clamped to this slot's list (always a valid address)
+        // the next step's codes, clamped to this block's list (always a valid address)
 #pragma unroll
         for (int u = 0; u < PU; ++u) cn[u] = codes[min(e + PU + u, e1 - 1)];
         // every load of the step is issued before the first multiply-add: without the
@@ -545,14 +395,14 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
         // few gathers in flight per wave
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < PU; ++u) contrib(xraw[u], yraw[u]);
+        for (int u = 0; u < PU; ++u) contrib(XS ? xblock(k[u]) : xraw[XS ? 0 : u], yraw[u]);
       }
     }
     for (; e < e1; ++e) {
       int k, q;
       place(codes[e], k, q);
-      TY yraw[BR * BC];
-      load_y<TY, VEC>(y_v + static_cast<size_t>(q) * (BR * BC), yraw);
+      TY yraw[BR * CW];
+      load_ycols<TY, VEC, BR, BC, CW>(y_v + static_cast<size_t>(q) * (BR * BC), c0, yraw);
       contrib(xblock(k), yraw);
     }
   };
@@ -563,17 +413,23 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
     walk(std::false_type{}, std::false_type{});
   }
   if constexpr (kIsAP) {
-    TA* o = static_cast<TA*>(out) + static_cast<size_t>(sidx) * (OR * BC);
+    TA* o = static_cast<TA*>(out) + static_cast<size_t>(sidx) * (OR * BC) + c0;
 #pragma unroll
-    for (int t = 0; t < OR * BC; ++t) o[t] = acc[t];
+    for (int r = 0; r < OR; ++r) {
+#pragma unroll
+      for (int cc = 0; cc < CW; ++cc) o[r * BC + cc] = acc[r * CW + cc];
+    }
   } else {
     // symmetric mode: slot sidx is the out_idx[sidx]-th block of C; its transpose
     // also goes to block mirror[sidx] (-1 on the diagonal)
     using TC = typename std::conditional<sizeof(TA) == 8, double, float>::type;
     const int64_t oi = out_idx ? out_idx[sidx] : sidx;
-    TC* o = static_cast<TC*>(out) + static_cast<size_t>(oi) * (OR * BC);
+    TC* o = static_cast<TC*>(out) + static_cast<size_t>(oi) * (OR * BC) + c0;
 #pragma unroll
-    for (int t = 0; t < OR * BC; ++t) st(o + t, acc[t]);
+    for (int r = 0; r < OR; ++r) {
+#pragma unroll
+      for (int cc = 0; cc < CW; ++cc) st(o + r * BC + cc, acc[r * CW + cc]);
+    }
     if (mirror) {
       const int mi = mirror[sidx];
       if (mi >= 0) {
@@ -581,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
 #pragma unroll
         for (int r = 0; r < OR; ++r) {
 #pragma unroll
-          for (int cc = 0; cc < BC; ++cc) st(o2 + cc * OR + r, acc[r * BC + cc]);
+          for (int cc = 0; cc < CW; ++cc) st(o2 + (c0 + cc) * OR + r, acc[r * CW + cc]);
         }
       }
     }
@@ -593,34 +449,44 @@ inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_
 template <int BR, int BC, class TA_, class TP, class TA, class CT>
 void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap, hipStream_t s) {
   const int64_t ns = pl.ap_nslots;
-  const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
+  const int spw = kBlock / pl.ap_nl;
+  const int grid = static_cast<int>((ns + spw - 1) / spw);
   if (grid == 0) return;
   // P blocks (BR*BC values) can be read with 2-element vector loads when the block
   // size is even and the array is aligned for it
   const bool vec = pl.ap_vec && (BR * BC) % 2 == 0 && aligned(P->val, 2 * sizeof(TP)) && sizeof(TP) >= 4;
   const size_t lds = ptap_lds_bytes(pl.ap_cap, kStageX<true, TA_> ? BR * BR * static_cast<int>(sizeof(TA_)) : 0);
-#define BLK_APK(V)                                                                                                   \
-  pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V><<<grid, kBlock, lds, s>>>(                                      \
+#define BLK_APK(V, NL)                                                                                               \
+  pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V, NL><<<grid, kBlock, lds, s>>>(                                      \
       ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
       static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_pairs.ptr.p,                                             \
       reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr, pl.ap_cap)
-  if (vec) BLK_APK(true); else BLK_APK(false);
+  if (pl.ap_nl == 3) {
+    if (vec) BLK_APK(true, 3); else BLK_APK(false, 3);
+  } else {
+    if (vec) BLK_APK(true, 1); else BLK_APK(false, 1);
+  }
 #undef BLK_APK
 }
 
 template <int BR, int BC, class TA_, class TP, class TA, class CT>
 void launch_rap_pairs(const PtapPlan& pl, const bsr_s* R, const bsr_s* C, const TA* ap, hipStream_t s) {
   const int64_t ns = pl.sym ? pl.c_nslots : C->nnzb;
-  const int grid = static_cast<int>((ns + kBlock - 1) / kBlock);
+  const int spw = kBlock / pl.c_nl;
+  const int grid = static_cast<int>((ns + spw - 1) / spw);
   if (grid == 0) return;
   const int32_t* orp = pl.sym ? pl.c_up_rp.p : C->rowptr;
   const size_t lds = ptap_lds_bytes(pl.c_cap, 0);
-#define BLK_RAPK(V)                                                                                                  \
-  pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V><<<grid, kBlock, lds, s>>>(                                      \
+#define BLK_RAPK(V, NL)                                                                                              \
+  pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V, NL><<<grid, kBlock, lds, s>>>(                                      \
       ns, C->nbr, pl.c_slot_row0.p, pl.c_perm.p, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, \
       ap, orp, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val,           \
       pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr, pl.c_cap)
-  if (pl.c_vec) BLK_RAPK(true); else BLK_RAPK(false);
+  if (pl.c_nl == 3) {
+    if (pl.c_vec) BLK_RAPK(true, 3); else BLK_RAPK(false, 3);
+  } else {
+    if (pl.c_vec) BLK_RAPK(true, 1); else BLK_RAPK(false, 1);
+  }
 #undef BLK_RAPK
 }
 
@@ -910,7 +776,17 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, orp, oci, true, plan->c_pairs);
     if (!plan->c_pairs.width) plan->sym = false;  // the searching kernel computes every block
     plan->ap_nslots = static_cast<int64_t>(apci.size());
-    const std::vector<int32_t> ap_w = first_rows(aprp, kBlock), c_w = first_rows(orp, kBlock);
+    // lanes per output block (tuning switches ap_nl1 / ap_nl3 / c_nl1 / c_nl3)
+    const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
+    const std::string tn = tune ? tune : "ap_sort";
+    auto has = [&](const char* f) { return tn.find(f) != std::string::npos; };
+    // Measured at 128^3: three lanes per block shorten every A P pass (FP64 fine level
+    // 8.0 -> 5.6 ms) and the 6x6 R AP passes; the fine FP32 R AP pass is faster with
+    // one lane per block (2.1 vs 2.3 ms).
+    plan->ap_nl = has("ap_nl1") ? 1 : 3;
+    plan->c_nl = has("c_nl1") ? 1 : has("c_nl3") ? 3 : (A->dtype == BLKAMG_F32 && A->br == 3 ? 1 : 3);
+    const int ap_spw = kBlock / plan->ap_nl, c_spw = kBlock / plan->c_nl;
+    const std::vector<int32_t> ap_w = first_rows(aprp, ap_spw), c_w = first_rows(orp, c_spw);
     upload(plan->ap_slot_row0, ap_w);
     upload(plan->c_slot_row0, c_w);
     // LDS capacity: the X extent that 99.5% of the workgroups fit in (the rest read
@@ -934,19 +810,17 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     };
     plan->ap_cap = cap_of(ap_w, A->h_rowptr, A->nbr, 4 + static_cast<size_t>(A->br) * A->br * dtype_size(A->dtype));
     plan->c_cap = cap_of(c_w, R->h_rowptr, R->nbr, 4);
-    // tuning switches (experiments): BLKAMG_PTAP_TUNE="ap_sort,c_sort,ap_novec,c_novec"
-    const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
-    const std::string tn = tune ? tune : "ap_sort";
-    auto has = [&](const char* f) { return tn.find(f) != std::string::npos; };
+    if (has("nostage")) plan->ap_cap = plan->c_cap = 1;  // every workgroup takes the global-memory path
+    // more tuning switches: ap_sort, c_sort, ap_novec, c_novec
     plan->ap_vec = !has("ap_novec");
     plan->c_vec = !has("c_novec");
     if (plan->ap_pairs.width) {
       std::vector<int32_t> hp = download(plan->ap_pairs.ptr.p, plan->ap_pairs.ptr.n);
-      upload(plan->ap_perm, has("ap_sort") ? count_order(hp, kBlock) : identity_order(hp.size() - 1, kBlock));
+      upload(plan->ap_perm, has("ap_sort") ? count_order(hp, ap_spw) : identity_order(hp.size() - 1, ap_spw));
     }
     if (plan->c_pairs.width) {
       std::vector<int32_t> hp = download(plan->c_pairs.ptr.p, plan->c_pairs.ptr.n);
-      upload(plan->c_perm, has("c_sort") ? count_order(hp, kBlock) : identity_order(hp.size() - 1, kBlock));
+      upload(plan->c_perm, has("c_sort") ? count_order(hp, c_spw) : identity_order(hp.size() - 1, c_spw));
     }
   }
   auto Cm = make_owned(P->nbc, P->nbc, P->bc, P->bc, A->dtype, std::move(crp), std::move(cci));

@@ -218,3 +218,30 @@ def test_ptap_symmetric_mode(bs):
             assert np.abs(got.val[t] - got.val[t].T).max() <= 1e-13 * np.abs(got.val[t]).max()
     with pytest.raises(B.BlkAmgError):
         B.ptap_symbolic_ex(HA, HP, 8)
+
+
+@pytest.mark.parametrize("bs", [3, 6])
+def test_ptap_lane_mappings_agree(bs, monkeypatch):
+    """One or three lanes per output block (each lane owning a share of its columns),
+    LDS-staged or global-memory workgroups: every mapping adds the same products in
+    the same order, so all give identical bits, within 1e-12 (FP64) / 1e-5 (FP32) of
+    the oracle."""
+    rp, ci, v = synth.random_spd_bsr(300, bs, seed=31, max_per_row=14)
+    A = S.Bsr(300, 300, bs, bs, rp.astype(np.int64), ci.astype(np.int64), v)
+    P = _rand(300, 41, bs, 6, seed=32, max_per_row=5)
+    want = S.ptap(A, P)
+    for dt, tol in ((B.F64, 1e-12), (B.F32, 1e-5)):
+        HA, _ = to_device_bsr(A, dt)
+        HP, _ = to_device_bsr(P, dt)
+        ref = None
+        for tune in ("ap_sort,ap_nl1,c_nl1", "ap_sort,ap_nl3,c_nl3", "ap_sort,ap_nl3,c_nl1",
+                     "ap_sort,ap_nl1,c_nl3,nostage", "ap_sort,ap_nl3,c_nl3,nostage"):
+            monkeypatch.setenv("BLKAMG_PTAP_TUNE", tune)
+            HC = B.ptap_symbolic_ex(HA, HP, B.PTAP_SYMMETRIC)
+            B.ptap_numeric(HA, HP, HC)
+            got = from_device_bsr(HC)
+            assert rel2(got.val, want.val) <= tol, tune
+            if ref is None:
+                ref = got.val.copy()
+            else:
+                assert np.array_equal(got.val, ref), tune
