@@ -536,6 +536,16 @@ void vcycle(amg_s* M, const double* r, double* z, int nr, hipStream_t s) {
   else vcycle_nr<8>(M, r, z, s);
 }
 
+// FP32 hierarchy, one right-hand side, input already in the fine level's FP32 buffer;
+// returns the FP32 output buffer (the caller widens it where it reads it)
+const float* vcycle_f32_in_place(amg_s* M, hipStream_t s) {
+  Level& L0 = *M->lv[0];
+  float* f = buf<float>(L0.f);
+  float* o = buf<float>(L0.out);
+  vcycle_level<float, 1>(M, 0, f, o, s);
+  return o;
+}
+
 // ---------------------------------------------------------------------------
 // Setup helpers
 // ---------------------------------------------------------------------------
@@ -1177,12 +1187,35 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
   if (iters) *iters = 0;
   if (relres) *relres = 0.0;
   if (bn == 0.0) return BLKAMG_OK;
-  vcycle(M, r, z, 1, s);
-  dot_kernel<<<vg, 256, 0, s>>>(n, r, z, M->partial.p);
-  HIP_CHECK(hipGetLastError());
-  reduce(M, vg, sc + S_RZ, R_STORE, s);
-  pcg_p_kernel<<<vgrid(n), 256, 0, s>>>(n, sc, 0, z, p);
-  HIP_CHECK(hipGetLastError());
+  // With an FP32 hierarchy the residual update also writes the V-cycle's FP32 input and
+  // the dot and direction updates read its FP32 output: no separate casts.
+  const bool mixed = M->T == BLKAMG_F32;
+  float* r32 = mixed ? buf<float>(M->lv[0]->f) : nullptr;
+  auto precondition = [&]() {
+    if (mixed) {
+      const float* z32 = vcycle_f32_in_place(M, s);
+      dot_kernel<float><<<vg, 256, 0, s>>>(n, r, z32, M->partial.p);
+      return z32;
+    }
+    vcycle(M, r, z, 1, s);
+    dot_kernel<double><<<vg, 256, 0, s>>>(n, r, z, M->partial.p);
+    return static_cast<const float*>(nullptr);
+  };
+  auto direction = [&](const float* z32, int use_beta) {
+    if (mixed) pcg_p_kernel<float><<<vgrid(n), 256, 0, s>>>(n, sc, use_beta, z32, p);
+    else pcg_p_kernel<double><<<vgrid(n), 256, 0, s>>>(n, sc, use_beta, z, p);
+    HIP_CHECK(hipGetLastError());
+  };
+  if (mixed) {
+    cast_vec_kernel<double, float><<<vgrid(n), 256, 0, s>>>(n, r, r32);
+    HIP_CHECK(hipGetLastError());
+  }
+  {
+    const float* z32 = precondition();
+    HIP_CHECK(hipGetLastError());
+    reduce(M, vg, sc + S_RZ, R_STORE, s);
+    direction(z32, 0);
+  }
   const int G = lanes_for(A, 1);
   bool converged = false;
   while (it < maxit) {
@@ -1192,7 +1225,7 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
                               : launch_rows<6, 6, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
                                                                             static_cast<const double*>(A->val), p, epi, s);
     reduce(M, sg, nullptr, R_ALPHA, s);
-    pcg_update_kernel<<<vg, 256, 0, s>>>(n, sc, p, w, d_x, r, M->partial.p);
+    pcg_update_kernel<<<vg, 256, 0, s>>>(n, sc, p, w, d_x, r, M->partial.p, r32);
     HIP_CHECK(hipGetLastError());
     reduce(M, vg, sc + S_RR, R_STORE, s);
     ++it;
@@ -1204,12 +1237,10 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
     }
     rn = std::sqrt(M->host_s[S_RR]);
     if (rn <= rtol * bn) { converged = true; break; }
-    vcycle(M, r, z, 1, s);
-    dot_kernel<<<vg, 256, 0, s>>>(n, r, z, M->partial.p);
+    const float* z32 = precondition();
     HIP_CHECK(hipGetLastError());
     reduce(M, vg, nullptr, R_BETA, s);
-    pcg_p_kernel<<<vgrid(n), 256, 0, s>>>(n, sc, 1, z, p);
-    HIP_CHECK(hipGetLastError());
+    direction(z32, 1);
   }
   if (iters) *iters = it;
   if (relres) *relres = rn / bn;

@@ -771,10 +771,12 @@ struct EpiPcgW {
   }
 };
 
+// x += alpha p, r -= alpha w, partial sums of r.r; with r32 set, also the FP32 copy of r
+// that an FP32 V-cycle takes as input (rounded to nearest)
 __global__ __launch_bounds__(256) void pcg_update_kernel(size_t n, const double* __restrict__ sc,
                                                          const double* __restrict__ p, const double* __restrict__ w,
                                                          double* __restrict__ x, double* __restrict__ r,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial, float* __restrict__ r32) {
   __shared__ double lds[4];
   double acc = 0.0;
   const double a = sc[S_ALPHA];
@@ -783,28 +785,33 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(size_t n, const double*
     x[g] = fmadd(a, p[g], x[g]);
     const double rv = fmadd(-a, w[g], r[g]);
     r[g] = rv;
+    if (r32) r32[g] = static_cast<float>(rv);
     acc = fmadd(rv, rv, acc);
   }
   const double t = block_sum_256(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void dot_kernel(size_t n, const double* __restrict__ a, const double* __restrict__ b,
+// partial sums of a.b; b may be the FP32 output of an FP32 V-cycle (widened exactly)
+template <class TB>
+__global__ __launch_bounds__(256) void dot_kernel(size_t n, const double* __restrict__ a, const TB* __restrict__ b,
                                                   double* __restrict__ partial) {
   __shared__ double lds[4];
   double acc = 0.0;
   for (size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; g < n;
        g += static_cast<size_t>(gridDim.x) * blockDim.x)
-    acc = fmadd(a[g], b[g], acc);
+    acc = fmadd(a[g], static_cast<double>(b[g]), acc);
   const double t = block_sum_256(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ void pcg_p_kernel(size_t n, const double* __restrict__ sc, int use_beta, const double* __restrict__ z,
+template <class TZ>
+__global__ void pcg_p_kernel(size_t n, const double* __restrict__ sc, int use_beta, const TZ* __restrict__ z,
                              double* __restrict__ p) {
   const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
   if (g >= n) return;
-  p[g] = use_beta ? fmadd(sc[S_BETA], p[g], z[g]) : z[g];
+  const double zv = static_cast<double>(z[g]);
+  p[g] = use_beta ? fmadd(sc[S_BETA], p[g], zv) : zv;
 }
 
 __global__ __launch_bounds__(256) void pcg_init_kernel(size_t n, const double* __restrict__ b, double* __restrict__ x,
