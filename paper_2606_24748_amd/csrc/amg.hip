@@ -211,10 +211,10 @@ void build_grid(amg_s* M, SegGrid& g, const std::vector<int64_t>& dof_off, int c
   }
 }
 
-template <int NR, class T, class Op>
-void seg_reduce(amg_s* M, const SegGrid& g, const T* a, const T* b, const Op& op, hipStream_t s) {
+template <int NR, class T, class Op, class TB = T>
+void seg_reduce(amg_s* M, const SegGrid& g, const T* a, const TB* b, const Op& op, hipStream_t s) {
   if (g.nseg == 0) return;
-  if (g.nchunk > 0) seg_dot_kernel<NR, T><<<g.nchunk, 256, 0, s>>>(a, b, g.lo.p, g.hi.p, M->partial.p);
+  if (g.nchunk > 0) seg_dot_kernel<NR, T, TB><<<g.nchunk, 256, 0, s>>>(a, b, g.lo.p, g.hi.p, M->partial.p);
   seg_finish_kernel<Op><<<g.nseg * NR, 256, 0, s>>>(M->partial.p, g.ptr.p, NR, op);
   HIP_CHECK(hipGetLastError());
 }
@@ -536,13 +536,14 @@ void vcycle(amg_s* M, const double* r, double* z, int nr, hipStream_t s) {
   else vcycle_nr<8>(M, r, z, s);
 }
 
-// FP32 hierarchy, one right-hand side, input already in the fine level's FP32 buffer;
-// returns the FP32 output buffer (the caller widens it where it reads it)
+// FP32 hierarchy, input already in the fine level's FP32 buffer; returns the FP32
+// output buffer (the caller widens it where it reads it)
+template <int NR = 1>
 const float* vcycle_f32_in_place(amg_s* M, hipStream_t s) {
   Level& L0 = *M->lv[0];
   float* f = buf<float>(L0.f);
   float* o = buf<float>(L0.out);
-  vcycle_level<float, 1>(M, 0, f, o, s);
+  vcycle_level<float, NR>(M, 0, f, o, s);
   return o;
 }
 
@@ -1264,12 +1265,22 @@ void bpcg_iteration(amg_s* M, bsr_s* A, double* x, double rtol, int maxit, hipSt
   const int vg = vgrid(nrow * NR);
   spmv(A, 1.0, p, 0.0, w, BLKAMG_F64, NR, s);
   seg_reduce<NR>(M, g, p, w, OpBAlpha{bs, stride, NR}, s);
-  bpcg_axpy_kernel<<<vg, 256, 0, s>>>(nrow, NR, off, nseg, bs, stride, p, w, x, r);
+  // with an FP32 hierarchy the update writes the V-cycle's FP32 input and the reads of
+  // its output widen FP32 values (no separate casts)
+  const bool mixed = M->T == BLKAMG_F32;
+  float* r32 = mixed ? buf<float>(M->lv[0]->f) : nullptr;
+  bpcg_axpy_kernel<<<vg, 256, 0, s>>>(nrow, NR, off, nseg, bs, stride, p, w, x, r, r32);
   HIP_CHECK(hipGetLastError());
   seg_reduce<NR>(M, g, r, r, OpBRr{bs, stride, NR, maxit, rtol}, s);
-  vcycle(M, r, z, NR, s);
-  seg_reduce<NR>(M, g, r, z, OpBBeta{bs, stride, NR}, s);
-  bpcg_p_kernel<<<vg, 256, 0, s>>>(nrow, NR, off, nseg, bs, stride, 1, z, p);
+  if (mixed) {
+    const float* z32 = vcycle_f32_in_place<NR>(M, s);
+    seg_reduce<NR>(M, g, r, z32, OpBBeta{bs, stride, NR}, s);
+    bpcg_p_kernel<float><<<vg, 256, 0, s>>>(nrow, NR, off, nseg, bs, stride, 1, z32, p);
+  } else {
+    vcycle(M, r, z, NR, s);
+    seg_reduce<NR>(M, g, r, z, OpBBeta{bs, stride, NR}, s);
+    bpcg_p_kernel<double><<<vg, 256, 0, s>>>(nrow, NR, off, nseg, bs, stride, 1, z, p);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
@@ -1343,9 +1354,17 @@ int pcg_batched(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol,
   bpcg_init_kernel<<<vgrid(n), 256, 0, s>>>(n, d_b, d_x, M->pr.p);
   HIP_CHECK(hipGetLastError());
   seg_reduce<NR>(M, g, d_b, d_b, OpBInit{bs, stride, NR, maxit}, s);
-  vcycle(M, M->pr.p, M->pz.p, NR, s);
-  seg_reduce<NR>(M, g, M->pr.p, M->pz.p, OpBRz0{bs, stride, NR}, s);
-  bpcg_p_kernel<<<vgrid(n), 256, 0, s>>>(nrow, NR, off, M->n_inst, bs, stride, 0, M->pz.p, M->pp.p);
+  if (M->T == BLKAMG_F32) {
+    cast_vec_kernel<double, float><<<vgrid(n), 256, 0, s>>>(n, M->pr.p, buf<float>(M->lv[0]->f));
+    HIP_CHECK(hipGetLastError());
+    const float* z32 = vcycle_f32_in_place<NR>(M, s);
+    seg_reduce<NR>(M, g, M->pr.p, z32, OpBRz0{bs, stride, NR}, s);
+    bpcg_p_kernel<float><<<vgrid(n), 256, 0, s>>>(nrow, NR, off, M->n_inst, bs, stride, 0, z32, M->pp.p);
+  } else {
+    vcycle(M, M->pr.p, M->pz.p, NR, s);
+    seg_reduce<NR>(M, g, M->pr.p, M->pz.p, OpBRz0{bs, stride, NR}, s);
+    bpcg_p_kernel<double><<<vgrid(n), 256, 0, s>>>(nrow, NR, off, M->n_inst, bs, stride, 0, M->pz.p, M->pp.p);
+  }
   HIP_CHECK(hipGetLastError());
   bpcg_status_kernel<<<1, 64, 0, s>>>(bs, stride, nsys, M->bstat.p);
   HIP_CHECK(hipGetLastError());

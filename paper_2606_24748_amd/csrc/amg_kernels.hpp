@@ -55,8 +55,8 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
 // Segmented dot products.  A chunk is a row range inside one segment; workgroup c
 // sums chunk c for every right-hand side q into partial[c * NR + q].
 // ---------------------------------------------------------------------------
-template <int NR, class T>
-__global__ __launch_bounds__(256) void seg_dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
+template <int NR, class T, class TB = T>
+__global__ __launch_bounds__(256) void seg_dot_kernel(const T* __restrict__ a, const TB* __restrict__ b,
                                                       const int32_t* __restrict__ lo, const int32_t* __restrict__ hi,
                                                       double* __restrict__ partial) {
   __shared__ double lds[4 * NR];
@@ -927,9 +927,12 @@ __global__ void bpcg_init_kernel(size_t n, const double* __restrict__ b, double*
 
 // x += alpha p ; r -= alpha w   (alpha of the element's system; systems with alpha = 0
 // are left untouched, so a stopped system keeps its x and r exactly)
+// x += alpha p, r -= alpha w per system (alpha = 0: frozen, untouched); with r32 set,
+// also the FP32 copy of r that an FP32 V-cycle takes as input
 __global__ void bpcg_axpy_kernel(size_t nrow, int nr, const int32_t* __restrict__ off, int nseg,
                                  const double* __restrict__ bs, int stride, const double* __restrict__ p,
-                                 const double* __restrict__ w, double* __restrict__ x, double* __restrict__ r) {
+                                 const double* __restrict__ w, double* __restrict__ x, double* __restrict__ r,
+                                 float* __restrict__ r32) {
   const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
   if (g >= nrow * nr) return;
   const int row = static_cast<int>(g / nr), q = static_cast<int>(g % nr);
@@ -937,16 +940,19 @@ __global__ void bpcg_axpy_kernel(size_t nrow, int nr, const int32_t* __restrict_
   const double a = bs[B_ALPHA * stride + sg * nr + q];
   if (a == 0.0) return;
   x[g] = fmadd(a, p[g], x[g]);
-  r[g] = fmadd(-a, w[g], r[g]);
+  const double rv = fmadd(-a, w[g], r[g]);
+  r[g] = rv;
+  if (r32) r32[g] = static_cast<float>(rv);
 }
 
 // p = z + beta p  (p = z on the first step or when beta = 0)
+template <class TZ>
 __global__ void bpcg_p_kernel(size_t nrow, int nr, const int32_t* __restrict__ off, int nseg,
-                              const double* __restrict__ bs, int stride, int use_beta, const double* __restrict__ z,
+                              const double* __restrict__ bs, int stride, int use_beta, const TZ* __restrict__ z,
                               double* __restrict__ p) {
   const size_t g = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
   if (g >= nrow * nr) return;
-  double v = z[g];
+  double v = static_cast<double>(z[g]);
   if (use_beta) {
     const int row = static_cast<int>(g / nr), q = static_cast<int>(g % nr);
     const int sg = nseg > 1 ? seg_of(off, nseg, row) : 0;
