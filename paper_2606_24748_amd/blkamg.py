@@ -24,6 +24,11 @@ MLP_PARAMS, MLP_MODEL = 5122, 5150
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2606_24748_amd/build.py (or __graft_entry__.build())")
 
+# torch is imported before the library is loaded: the library then binds to the HIP
+# runtime torch has already loaded (same soname).  Loaded first, it would bring a second
+# HIP/HSA runtime into the process, and torch would then report no GPU.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 _p = C.c_void_p

@@ -77,3 +77,16 @@ def test_default_options():
     assert (o.max_levels, o.coarse_eq_limit, o.cheb_degree, o.lanczos_steps) == (10, 1000, 2, 10)
     assert (o.cheb_lo, o.cheb_hi, o.strength_eps) == (0.1, 1.1, 0.0)
     assert o.lanczos_seed == 0x5EED and abs(o.omega_scale - 4 / 3) < 1e-15
+
+
+def test_single_hip_runtime_after_import():
+    """Importing the binding (before anything else imports torch) leaves one HIP runtime
+    in the process: the library binds to torch's, whatever the import order."""
+    import subprocess
+    import sys
+    code = ("import paper_2606_24748_amd.blkamg, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
