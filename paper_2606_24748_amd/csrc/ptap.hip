@@ -41,6 +41,7 @@ struct PtapPlan {
   DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
   int ap_cap = 0, c_cap = 0;                   // LDS capacity (entries of X rows) of a workgroup
   int ap_nl = 1, c_nl = 1;                     // lanes per output block (1 or 3)
+  bool ap_xcd = false, c_xcd = false;          // XCD-contiguous workgroup order
   bool ap_vec = true, c_vec = true;
   // symmetric mode: only blocks with column >= row are computed (upper list), each
   // off-diagonal one is also stored transposed at its mirror position
@@ -220,7 +221,8 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
                                                             const int32_t* __restrict__ pp, const CT* __restrict__ codes,
                                                             int shift, void* __restrict__ out,
                                                             const int32_t* __restrict__ out_idx,
-                                                            const int32_t* __restrict__ mirror, int cap) {
+                                                            const int32_t* __restrict__ mirror, int cap,
+                                                            bool xcd_map) {
   // kIsAP: X = A (BR x BR), Y = P (BR x BC), out AP (BR x BC) in TA
   // else : X = R (BC x BR), Y = AP (BR x BC), out C (BC x BC) in the type of A
   constexpr int XR = kIsAP ? BR : BC;  // rows of an X block
@@ -238,7 +240,10 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   extern __shared__ __align__(16) unsigned char ptap_lds[];
   int32_t* ystart = reinterpret_cast<int32_t*>(ptap_lds);
   TX* xs = reinterpret_cast<TX*>(ptap_lds + ((cap * 4 + 15) & ~15));
-  const int w = xcd_logical_block(blockIdx.x, gridDim.x);
+  // xcd_map: each XCD takes a contiguous range of workgroups (its L2 sees neighbouring
+  // rows); otherwise the hardware's round-robin order, where all XCDs work on one region
+  // at a time and the shared MALL holds what they gather
+  const int w = xcd_map ? xcd_logical_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
   const int64_t s_begin = static_cast<int64_t>(w) * SPW;
   const int row0 = slot_row0[w];
   const int row1 = min(nrows - 1, slot_row0[w + 1]);
@@ -460,7 +465,8 @@ void launch_ap_pairs(const PtapPlan& pl, const bsr_s* A, const bsr_s* P, TA* ap,
   pairs_slot_kernel<BR, BC, TA_, TP, TA, CT, true, V, NL><<<grid, kBlock, lds, s>>>(                                      \
       ns, A->nbr, pl.ap_slot_row0.p, pl.ap_perm.p, A->rowptr, A->colidx, static_cast<const TA_*>(A->val), P->rowptr, \
       static_cast<const TP*>(P->val), pl.ap_rowptr.p, pl.ap_pairs.ptr.p,                                             \
-      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr, pl.ap_cap)
+      reinterpret_cast<const CT*>(pl.ap_pairs.codes.p), pl.ap_pairs.shift, ap, nullptr, nullptr, pl.ap_cap,      \
+      pl.ap_xcd)
   if (pl.ap_nl == 3) {
     if (vec) BLK_APK(true, 3); else BLK_APK(false, 3);
   } else {
@@ -481,7 +487,7 @@ void launch_rap_pairs(const PtapPlan& pl, const bsr_s* R, const bsr_s* C, const 
   pairs_slot_kernel<BR, BC, TP, TA, TA, CT, false, V, NL><<<grid, kBlock, lds, s>>>(                                      \
       ns, C->nbr, pl.c_slot_row0.p, pl.c_perm.p, R->rowptr, R->colidx, static_cast<const TP*>(R->val), pl.ap_rowptr.p, \
       ap, orp, pl.c_pairs.ptr.p, reinterpret_cast<const CT*>(pl.c_pairs.codes.p), pl.c_pairs.shift, C->val,           \
-      pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr, pl.c_cap)
+      pl.sym ? pl.c_up_idx.p : nullptr, pl.sym ? pl.c_mirror.p : nullptr, pl.c_cap, pl.c_xcd)
   if (pl.c_nl == 3) {
     if (pl.c_vec) BLK_RAPK(true, 3); else BLK_RAPK(false, 3);
   } else {
@@ -783,6 +789,11 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     // Measured at 128^3: three lanes per block shorten every A P pass (FP64 fine level
     // 8.0 -> 5.6 ms) and the 6x6 R AP passes; the fine FP32 R AP pass is faster with
     // one lane per block (2.1 vs 2.3 ms).
+    // workgroup order: the hardware's round-robin over XCDs by default (measured at 128^3:
+    // 4-6 % faster for the fine passes than XCD-contiguous ranges, whose eight separate
+    // working sets overflow the shared MALL); ap_xcd / c_xcd switch back
+    plan->ap_xcd = has("ap_xcd");
+    plan->c_xcd = has("c_xcd");
     plan->ap_nl = has("ap_nl1") ? 1 : 3;
     plan->c_nl = has("c_nl1") ? 1 : has("c_nl3") ? 3 : (A->dtype == BLKAMG_F32 && A->br == 3 ? 1 : 3);
     const int ap_spw = kBlock / plan->ap_nl, c_spw = kBlock / plan->c_nl;
