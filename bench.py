@@ -77,7 +77,7 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per cube edge")
-    ap.add_argument("--variants", default="mixed,mixed-mlp,fp64",
+    ap.add_argument("--variants", default="mixed,mixed-mlp,mixed-bf16,fp64",
                     help="comma list of mixed, mixed-mlp, mixed-bf16, fp64")
     ap.add_argument("--probe-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
