@@ -41,7 +41,7 @@ struct PtapPlan {
   DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
   int ap_cap = 0, c_cap = 0;                   // LDS capacity (entries of X rows) of a workgroup
   int ap_nl = 1, c_nl = 1;                     // lanes per output block (1 or 3)
-  bool ap_xcd = false, c_xcd = false;          // XCD-contiguous workgroup order
+  int ap_xcd = 32, c_xcd = 8;                  // workgroup order: 0 hardware, -1 XCD-contiguous, C > 0 chunks
   bool ap_vec = true, c_vec = true;
   // symmetric mode: only blocks with column >= row are computed (upper list), each
   // off-diagonal one is also stored transposed at its mirror position
@@ -51,6 +51,18 @@ struct PtapPlan {
 };
 
 namespace {
+
+// Logical workgroup for hardware workgroup b (dispatched round-robin over the XCDs):
+// each XCD takes runs of `chunk` consecutive logical workgroups, and the runs rotate
+// over the XCDs, so every XCD works near the same region while neighbours within a run
+// share one L2.  A bijection on 0..n-1 (the incomplete last round keeps hardware order).
+__device__ __forceinline__ int xcd_chunked_block(int b, int n, int chunk) {
+  const int round = kNumXcd * chunk;
+  const int full = (n / round) * round;
+  if (b >= full) return b;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return (k / chunk) * round + x * chunk + (k % chunk);
+}
 
 __device__ __forceinline__ int search(const int32_t* __restrict__ cols, int lo, int hi, int key) {
   while (lo < hi) {
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
                                                             int shift, void* __restrict__ out,
                                                             const int32_t* __restrict__ out_idx,
                                                             const int32_t* __restrict__ mirror, int cap,
-                                                            bool xcd_map) {
+                                                            int xcd_chunk) {
   // kIsAP: X = A (BR x BR), Y = P (BR x BC), out AP (BR x BC) in TA
   // else : X = R (BC x BR), Y = AP (BR x BC), out C (BC x BC) in the type of A
   constexpr int XR = kIsAP ? BR : BC;  // rows of an X block
@@ -243,7 +255,9 @@ __global__ __launch_bounds__(kBlock) void pairs_slot_kernel(int64_t nslots, int 
   // xcd_map: each XCD takes a contiguous range of workgroups (its L2 sees neighbouring
   // rows); otherwise the hardware's round-robin order, where all XCDs work on one region
   // at a time and the shared MALL holds what they gather
-  const int w = xcd_map ? xcd_logical_block(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+  const int w = xcd_chunk < 0   ? xcd_logical_block(blockIdx.x, gridDim.x)
+                : xcd_chunk == 0 ? static_cast<int>(blockIdx.x)
+                                 : xcd_chunked_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), xcd_chunk);
   const int64_t s_begin = static_cast<int64_t>(w) * SPW;
   const int row0 = slot_row0[w];
   const int row1 = min(nrows - 1, slot_row0[w + 1]);
@@ -792,8 +806,17 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     // workgroup order: the hardware's round-robin over XCDs by default (measured at 128^3:
     // 4-6 % faster for the fine passes than XCD-contiguous ranges, whose eight separate
     // working sets overflow the shared MALL); ap_xcd / c_xcd switch back
-    plan->ap_xcd = has("ap_xcd");
-    plan->c_xcd = has("c_xcd");
+    // (ap_xcd / c_xcd: XCD-contiguous ranges; ap_xcd=C / c_xcd=C: chunks of C; measured at
+    // 128^3, runs of 32 (A P) and 8 (R AP) workgroups per XCD are 1-3 % faster again than
+    // the hardware order)
+    auto chunk_of = [&](const char* key, int dflt) {
+      const size_t at = tn.find(key);
+      if (at == std::string::npos) return dflt;
+      const char* v = tn.c_str() + at + std::strlen(key);
+      return *v == '=' ? std::max(0, std::atoi(v + 1)) : -1;
+    };
+    plan->ap_xcd = chunk_of("ap_xcd", 32);
+    plan->c_xcd = chunk_of("c_xcd", 8);
     plan->ap_nl = has("ap_nl1") ? 1 : 3;
     plan->c_nl = has("c_nl1") ? 1 : has("c_nl3") ? 3 : (A->dtype == BLKAMG_F32 && A->br == 3 ? 1 : 3);
     const int ap_spw = kBlock / plan->ap_nl, c_spw = kBlock / plan->c_nl;

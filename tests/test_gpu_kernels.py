@@ -236,7 +236,8 @@ def test_ptap_lane_mappings_agree(bs, monkeypatch):
         ref = None
         for tune in ("ap_sort,ap_nl1,c_nl1", "ap_sort,ap_nl3,c_nl3", "ap_sort,ap_nl3,c_nl1",
                      "ap_sort,ap_nl1,c_nl3,nostage", "ap_sort,ap_nl3,c_nl3,nostage",
-                     "ap_sort,ap_nl3,c_nl1,ap_xcd,c_xcd"):
+                     "ap_sort,ap_nl3,c_nl1,ap_xcd,c_xcd", "ap_sort,ap_nl3,c_nl3,ap_xcd=0,c_xcd=0",
+                     "ap_sort,ap_nl3,c_nl3,ap_xcd=3,c_xcd=5"):
             monkeypatch.setenv("BLKAMG_PTAP_TUNE", tune)
             HC = B.ptap_symbolic_ex(HA, HP, B.PTAP_SYMMETRIC)
             B.ptap_numeric(HA, HP, HC)
