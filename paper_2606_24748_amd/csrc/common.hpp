@@ -167,6 +167,21 @@ __device__ __forceinline__ int xcd_logical_block(int hw_block, int nblocks) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Rotating runs: each XCD takes runs of `chunk` consecutive logical blocks and the runs
+// rotate over the XCDs.  Neighbouring blocks within a run share one L2, while all XCDs
+// work near the same region at any time, so the shared MALL holds what they reuse.
+// Measured on the fine 3x3 SpMV at 128^3: runs of 32-64 workgroups are 4-7 % faster
+// than one contiguous range per XCD.  A bijection on 0..n-1 (the incomplete last round
+// keeps the hardware order).
+__device__ __forceinline__ int xcd_chunked_block(int hw_block, int nblocks, int chunk) {
+  const int round = kNumXcd * chunk;
+  const int full = (nblocks / round) * round;
+  if (hw_block >= full) return hw_block;
+  const int x = hw_block % kNumXcd, k = hw_block / kNumXcd;
+  return (k / chunk) * round + x * chunk + (k % chunk);
+}
+constexpr int kSpmvChunk = 64;
+
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 // sum over the G lanes of a group (G a power of two <= 64), result in all lanes

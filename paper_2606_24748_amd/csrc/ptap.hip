@@ -52,18 +52,6 @@ struct PtapPlan {
 
 namespace {
 
-// Logical workgroup for hardware workgroup b (dispatched round-robin over the XCDs):
-// each XCD takes runs of `chunk` consecutive logical workgroups, and the runs rotate
-// over the XCDs, so every XCD works near the same region while neighbours within a run
-// share one L2.  A bijection on 0..n-1 (the incomplete last round keeps hardware order).
-__device__ __forceinline__ int xcd_chunked_block(int b, int n, int chunk) {
-  const int round = kNumXcd * chunk;
-  const int full = (n / round) * round;
-  if (b >= full) return b;
-  const int x = b % kNumXcd, k = b / kNumXcd;
-  return (k / chunk) * round + x * chunk + (k % chunk);
-}
-
 __device__ __forceinline__ int search(const int32_t* __restrict__ cols, int lo, int hi, int key) {
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;

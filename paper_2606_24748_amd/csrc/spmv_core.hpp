@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
                                                       const TM* __restrict__ val,
                                                       const TX* __restrict__ x, Epi epi) {
   constexpr int kRows = kBlock / G;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_chunked_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), kSpmvChunk);
   const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
   const int lane = static_cast<int>(threadIdx.x) % G;
   TA acc[BR * NR];
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void spmm8_kernel(int nbr, const int32_t* _
   constexpr int NR = 8;
   static_assert(G >= NR, "eight right-hand sides need G >= 8");
   constexpr int kRows = kBlock / G;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_chunked_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), kSpmvChunk);
   const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
   const int lane = static_cast<int>(threadIdx.x) % G;
   TA v[NR * BR];  // v[q * BR + i]: row i of the block row, column q
