@@ -429,8 +429,7 @@ void coarse_factor(amg_s* M, Level& L, hipStream_t s) {
     if (m > 0) chol_update_kernel<<<dim3(m * (m + 1) / 2, L.n_term), 256, 0, s>>>(L.tL.p, L.t_mat_off.p, L.t_ndof.p, k);
   }
   HIP_CHECK(hipGetLastError());
-  for (int I = 0; I < nt; ++I)
-    tri_inverse_row_kernel<<<dim3(I + 1, L.n_term), 256, 0, s>>>(L.tL.p, L.tY.p, L.t_mat_off.p, L.t_ndof.p, I);
+  tri_inverse_col_kernel<<<dim3(nt, L.n_term), 256, 0, s>>>(L.tL.p, L.tY.p, L.t_mat_off.p, L.t_ndof.p);
   HIP_CHECK(hipGetLastError());
   transpose_dense_kernel<<<dim3(vgrid(static_cast<size_t>(L.t_max_nn)), L.n_term), 256, 0, s>>>(
       L.tY.p, L.tYt.p, L.t_mat_off.p, L.t_ndof.p);

@@ -114,37 +114,60 @@ struct OpLzAlpha {
 // Block-diagonal inverse (point-block Jacobi, paper §4.1)
 // ---------------------------------------------------------------------------
 template <int BS, class TM, class TD>
-__global__ void dinv_kernel(int nbr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+__global__ __launch_bounds__(256) void dinv_kernel(int nbr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                             const TM* __restrict__ val, TD* __restrict__ dinv, int32_t* __restrict__ diag_idx,
                             int* flag) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nbr) return;
+  // the diagonal block: binary search in the row's ascending column indices
   int kd = -1;
-  for (int k = rp[r]; k < rp[r + 1]; ++k)
-    if (ci[k] == r) { kd = k; break; }
+  for (int lo = rp[r], hi = rp[r + 1]; lo < hi;) {
+    const int mid = (lo + hi) >> 1;
+    const int c = ci[mid];
+    if (c == r) { kd = mid; break; }
+    if (c < r) lo = mid + 1; else hi = mid;
+  }
   diag_idx[r] = kd;
   double a[BS][2 * BS];
-  for (int i = 0; i < BS; ++i)
+#pragma unroll
+  for (int i = 0; i < BS; ++i) {
+#pragma unroll
     for (int j = 0; j < BS; ++j) {
       a[i][j] = kd >= 0 ? ld<double>(val + static_cast<size_t>(kd) * BS * BS + i * BS + j) : 0.0;
       a[i][BS + j] = (i == j) ? 1.0 : 0.0;
     }
-  bool ok = kd >= 0;  // Gauss-Jordan with partial pivoting
-  for (int c = 0; c < BS && ok; ++c) {
+  }
+  // Gauss-Jordan with partial pivoting, fully unrolled: the pivot row is exchanged with
+  // row c by selects, so every index is a compile-time constant and the array stays in
+  // registers (indexing it by the run-time pivot put it in scratch memory)
+  bool ok = kd >= 0;
+#pragma unroll
+  for (int c = 0; c < BS; ++c) {
     int p = c;
     double best = fabs(a[c][c]);
+#pragma unroll
     for (int i = c + 1; i < BS; ++i)
       if (fabs(a[i][c]) > best) { best = fabs(a[i][c]); p = i; }
-    if (!(best > 0.0)) { ok = false; break; }
-    if (p != c)
-      for (int j = 0; j < 2 * BS; ++j) { const double t = a[c][j]; a[c][j] = a[p][j]; a[p][j] = t; }
-    const double inv = 1.0 / a[c][c];
+    ok = ok && best > 0.0;
+#pragma unroll
+    for (int i = c + 1; i < BS; ++i) {
+      const bool sw = i == p;
+#pragma unroll
+      for (int j = 0; j < 2 * BS; ++j) {
+        const double t = a[c][j];
+        a[c][j] = sw ? a[i][j] : t;
+        a[i][j] = sw ? t : a[i][j];
+      }
+    }
+    const double inv = ok ? 1.0 / a[c][c] : 0.0;
+#pragma unroll
     for (int j = 0; j < 2 * BS; ++j) a[c][j] *= inv;
+#pragma unroll
     for (int i = 0; i < BS; ++i) {
       if (i == c) continue;
       const double f = a[i][c];
-      if (f != 0.0)
-        for (int j = 0; j < 2 * BS; ++j) a[i][j] -= f * a[c][j];
+#pragma unroll
+      for (int j = 0; j < 2 * BS; ++j) a[i][j] -= f * a[c][j];
     }
   }
   if (!ok) atomicExch(flag, 1);
@@ -636,55 +659,79 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ m
   }
 }
 
-// Block row I of Y = L^-1: Y_IJ = L_II^-1 (delta_IJ - sum_{K=J}^{I-1} L_IK Y_KJ), block x = J.
-__global__ __launch_bounds__(256) void tri_inverse_row_kernel(const double* __restrict__ Ls, double* __restrict__ Ys,
+// Column block J of Y = L^-1 by block forward substitution,
+//   Y_IJ = L_II^-1 (delta_IJ - sum_{K=J}^{I-1} L_IK Y_KJ),  I = J .. nt-1,
+// one workgroup per column block (block x = J), all of Y in one launch: the columns
+// are independent, and each workgroup reads back only tiles it wrote itself (visible
+// after the block barrier).
+__global__ __launch_bounds__(256) void tri_inverse_col_kernel(const double* __restrict__ Ls, double* __restrict__ Ys,
                                                               const int64_t* __restrict__ mat_off,
-                                                              const int32_t* __restrict__ ndof, int I) {
+                                                              const int32_t* __restrict__ ndof) {
   __shared__ double Dd[kT][kT + 1];
   __shared__ double S[kT][kT + 1];
   __shared__ double A[kT][kT + 1];
   __shared__ double Bt[kT][kT + 1];
   const int n = ndof[blockIdx.y];
+  const int nt = tiles_of(n);
   const int J = blockIdx.x;
-  if (I >= tiles_of(n) || J > I) return;
+  if (J >= nt) return;  // uniform over the block
   const double* L = Ls + mat_off[blockIdx.y];
   double* Y = Ys + mat_off[blockIdx.y];
-  const int ri = I * kT, cj = J * kT;
-  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-    const int i = e / kT, j = e % kT;
-    Dd[i][j] = mat_at(L, n, ri + i, ri + j);
-    S[i][j] = (I == J && i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int K = J; K < I; ++K) {
-    const int rk = K * kT;
+  const int cj = J * kT;
+  for (int I = J; I < nt; ++I) {
+    const int ri = I * kT;
     for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
       const int i = e / kT, j = e % kT;
-      A[i][j] = (ri + i < n && rk + j < n) ? L[static_cast<size_t>(ri + i) * n + rk + j] : 0.0;
-      Bt[i][j] = (rk + i < n && cj + j < n) ? Y[static_cast<size_t>(rk + i) * n + cj + j] : 0.0;
+      Dd[i][j] = mat_at(L, n, ri + i, ri + j);
+      S[i][j] = (I == J && i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-      const int i = e / kT, j = e % kT;
-      double sdot = 0.0;
+    // the tiles of step K + 1 are loaded into registers while step K multiplies
+    constexpr int kPer = kT * kT / 256;  // elements of a tile per thread
+    double na[kPer], nb[kPer];
+    auto fetch = [&](int K) {
+      const int rk = K * kT;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = static_cast<int>(threadIdx.x) + u * 256;
+        const int i = e / kT, j = e % kT;
+        na[u] = (ri + i < n && rk + j < n) ? L[static_cast<size_t>(ri + i) * n + rk + j] : 0.0;
+        nb[u] = (rk + i < n && cj + j < n) ? Y[static_cast<size_t>(rk + i) * n + cj + j] : 0.0;
+      }
+    };
+    if (J < I) fetch(J);
+    for (int K = J; K < I; ++K) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = static_cast<int>(threadIdx.x) + u * 256;
+        A[e / kT][e % kT] = na[u];
+        Bt[e / kT][e % kT] = nb[u];
+      }
+      __syncthreads();
+      if (K + 1 < I) fetch(K + 1);
+      for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+        const int i = e / kT, j = e % kT;
+        double sdot = 0.0;
 #pragma unroll 8
-      for (int q = 0; q < kT; ++q) sdot += A[i][q] * Bt[q][j];
-      S[i][j] -= sdot;
+        for (int q = 0; q < kT; ++q) sdot += A[i][q] * Bt[q][j];
+        S[i][j] -= sdot;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < kT) {  // forward substitution L_II y = s, column j by thread j
+      const int j = threadIdx.x;
+      for (int i = 0; i < kT; ++i) {
+        double v = S[i][j];
+        for (int q = 0; q < i; ++q) v -= Dd[i][q] * S[q][j];
+        S[i][j] = v / Dd[i][i];
+      }
     }
     __syncthreads();
-  }
-  if (threadIdx.x < kT) {  // forward substitution L_II y = s, column j by thread j
-    const int j = threadIdx.x;
-    for (int i = 0; i < kT; ++i) {
-      double v = S[i][j];
-      for (int q = 0; q < i; ++q) v -= Dd[i][q] * S[q][j];
-      S[i][j] = v / Dd[i][i];
+    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+      const int i = e / kT, j = e % kT;
+      if (ri + i < n && cj + j < n) Y[static_cast<size_t>(ri + i) * n + cj + j] = S[i][j];
     }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-    const int i = e / kT, j = e % kT;
-    if (ri + i < n && cj + j < n) Y[static_cast<size_t>(ri + i) * n + cj + j] = S[i][j];
+    __syncthreads();  // this tile is read back (as Y_KJ) by the next block rows
   }
 }
 
