@@ -73,6 +73,7 @@ extern "C" {
 typedef struct bsr_s* bsr_t;
 typedef struct coo_plan_s* coo_plan_t;
 typedef struct amg_s* amg_t;
+typedef struct sa_result_s* sa_result_t;
 
 /* Thread-local text of the last error ("" if none).  Never NULL. */
 const char* blkamg_last_error(void);
@@ -226,6 +227,33 @@ void blkamg_opts_default(blkamg_opts* o);
  * h_rowptr/h_colidx: host pattern.  h_dirichlet may be NULL.  Pure host code. */
 int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
                  const uint8_t* h_dirichlet, int32_t* h_agg, int32_t* n_agg);
+
+/* One smoothed-aggregation level on the host from the fine block pattern (paper §2.2,
+ * §3.2): the greedy aggregation of sa_aggregate, the tentative prolongator P~ of the
+ * six rigid-body modes built from h_coords ([n_nodes][3], bs = 3: per aggregate a thin
+ * Householder QR of its members' rows in ascending order, signs with diag(R) > 0), the
+ * coarse near-null space R ([n_agg][6][6]) and the pattern of the smoothed prolongator
+ * (the structural product of the pattern of A with that of P~; the values follow from
+ * D^-1 A on the device).  h_rowptr / h_colidx: the pattern of A with strictly ascending
+ * columns per row; h_dirichlet ([n_nodes] flags, may be NULL) excludes rows from the
+ * aggregation.  opts may be NULL; its strength_eps must be 0 (no values are given).
+ * The arrays belong to the result: read them with sa_result_info / sa_result_arrays,
+ * release them with sa_result_free.  EINVAL on a malformed pattern or a rank-deficient
+ * aggregate.  Pure host code. */
+int sa_setup_host(int32_t n_nodes, const int32_t* h_rowptr, const int32_t* h_colidx,
+                  const uint8_t* h_dirichlet, const double* h_coords, const blkamg_opts* opts,
+                  sa_result_t* out);
+/* Sizes of a result: aggregates, blocks of P~ (one per aggregated row), blocks of the
+ * smoothed-prolongator pattern (any pointer may be NULL). */
+int sa_result_info(sa_result_t r, int32_t* n_agg, int64_t* pt_nnzb, int64_t* sp_nnzb);
+/* Host arrays of a result, valid until sa_result_free (any pointer may be NULL):
+ * agg [n_nodes] (aggregate id, -1 for unaggregated rows); P~ as BSR with 3x6 blocks:
+ * pt_rowptr [n_nodes + 1], pt_colidx [pt_nnzb], pt_val [pt_nnzb][3][6] row-major;
+ * bc [n_agg][6][6]; smoothed pattern sp_rowptr [n_nodes + 1], sp_colidx [sp_nnzb]. */
+int sa_result_arrays(sa_result_t r, const int32_t** agg, const int32_t** pt_rowptr,
+                     const int32_t** pt_colidx, const double** pt_val, const double** bc,
+                     const int32_t** sp_rowptr, const int32_t** sp_colidx);
+int sa_result_free(sa_result_t r);
 
 /* Build the hierarchy from the fine operator A0 (square blocks bs = A0.bs_r, F64):
  * per level aggregate, tentative prolongator from the near-null space (thin QR per

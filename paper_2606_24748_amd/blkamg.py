@@ -78,6 +78,10 @@ _SIG = {
     "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
     "blkamg_opts_default": (None, [C.POINTER(Opts)]),
     "sa_aggregate": (C.c_int, [_i32, _p, _p, _p, _p, _pi32]),
+    "sa_setup_host": (C.c_int, [_i32, _p, _p, _p, _p, C.POINTER(Opts), C.POINTER(_p)]),
+    "sa_result_info": (C.c_int, [_p, _pi32, C.POINTER(_i64), C.POINTER(_i64)]),
+    "sa_result_arrays": (C.c_int, [_p] + [C.POINTER(_p)] * 7),
+    "sa_result_free": (C.c_int, [_p]),
     "amg_setup": (C.c_int, [_p, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
     "amg_setup_batched": (C.c_int, [_p, _i32, _p, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
     "amg_destroy": (C.c_int, [_p]),
@@ -310,6 +314,45 @@ def sa_aggregate(rowptr: np.ndarray, colidx: np.ndarray, dirichlet=None):
     _check(_lib.sa_aggregate(nbr, rowptr.ctypes.data_as(_p), colidx.ctypes.data_as(_p), d,
                              agg.ctypes.data_as(_p), C.byref(n)), "sa_aggregate")
     return agg, n.value
+
+
+def sa_setup_host(rowptr: np.ndarray, colidx: np.ndarray, coords: np.ndarray, dirichlet=None) -> dict:
+    """Host setup of one aggregation level from the fine block pattern (sa_setup_host):
+    copies of agg, the tentative prolongator (pt_rowptr, pt_colidx, pt_val [nnzb,3,6]),
+    the coarse near-null space bc [n_agg,6,6] and the smoothed-prolongator pattern."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    n = len(rowptr) - 1
+    d = None
+    if dirichlet is not None:
+        dd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        d = dd.ctypes.data_as(_p)
+    h = _p()
+    _check(_lib.sa_setup_host(n, rowptr.ctypes.data_as(_p), colidx.ctypes.data_as(_p), d,
+                              coords.ctypes.data_as(_p), None, C.byref(h)), "sa_setup_host")
+    try:
+        na, pn, sn = _i32(), _i64(), _i64()
+        _check(_lib.sa_result_info(h, C.byref(na), C.byref(pn), C.byref(sn)), "sa_result_info")
+        ptrs = [_p() for _ in range(7)]
+        _check(_lib.sa_result_arrays(h, *[C.byref(q) for q in ptrs]), "sa_result_arrays")
+
+        def arr(q, count, ctype, dtype):
+            if count == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(C.cast(q, C.POINTER(ctype)), shape=(count,)).astype(dtype, copy=True)
+
+        out = {"n_agg": na.value,
+               "agg": arr(ptrs[0], n, C.c_int32, np.int32),
+               "pt_rowptr": arr(ptrs[1], n + 1, C.c_int32, np.int32),
+               "pt_colidx": arr(ptrs[2], pn.value, C.c_int32, np.int32),
+               "pt_val": arr(ptrs[3], pn.value * 18, C.c_double, np.float64).reshape(pn.value, 3, 6),
+               "bc": arr(ptrs[4], na.value * 36, C.c_double, np.float64).reshape(na.value, 6, 6),
+               "sp_rowptr": arr(ptrs[5], n + 1, C.c_int32, np.int32),
+               "sp_colidx": arr(ptrs[6], sn.value, C.c_int32, np.int32)}
+    finally:
+        _lib.sa_result_free(h)
+    return out
 
 
 class Amg:

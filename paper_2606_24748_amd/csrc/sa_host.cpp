@@ -6,9 +6,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <string>
 
 #include "common.hpp"
+#include "internal.hpp"
 
 namespace blk {
 
@@ -191,5 +193,87 @@ extern "C" int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t*
   std::vector<int32_t> agg;
   *n_agg = blk::aggregate_host(nbr, h_rowptr, h_colidx, h_dirichlet, nullptr, agg);
   std::copy(agg.begin(), agg.end(), h_agg);
+  BLK_API_END
+}
+
+// Host setup of one smoothed-aggregation level from a block pattern (paper §2.2):
+// aggregation, tentative prolongator, coarse near-null space and the pattern of the
+// smoothed prolongator.
+struct sa_result_s {
+  int32_t n_nodes = 0, n_agg = 0;
+  std::vector<int32_t> agg;
+  std::vector<int32_t> pt_rowptr, pt_colidx;  // P~: one block per aggregated row
+  std::vector<double> pt_val;                 // [pt_nnzb][3][6]
+  std::vector<double> bc;                     // [n_agg][6][6]
+  std::vector<int32_t> sp_rowptr, sp_colidx;  // pattern of A P~
+};
+
+extern "C" int sa_setup_host(int32_t n_nodes, const int32_t* h_rowptr, const int32_t* h_colidx,
+                             const uint8_t* h_dirichlet, const double* h_coords, const blkamg_opts* opts,
+                             sa_result_t* out) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(out != nullptr, BLKAMG_EINVAL, "output pointer is NULL");
+  *out = nullptr;
+  BLK_REQUIRE(n_nodes >= 0 && h_rowptr != nullptr, BLKAMG_EINVAL, "bad size or NULL rowptr");
+  BLK_REQUIRE(n_nodes == 0 || h_coords != nullptr, BLKAMG_EINVAL, "coordinates are NULL");
+  BLK_REQUIRE(h_rowptr[0] == 0 && (h_rowptr[n_nodes] == 0 || h_colidx != nullptr), BLKAMG_EINVAL, "bad rowptr");
+  BLK_REQUIRE(opts == nullptr || opts->strength_eps == 0.0, BLKAMG_EINVAL,
+              "a pattern-only setup has no block norms: strength_eps must be 0");
+  for (int32_t r = 0; r < n_nodes; ++r) {
+    BLK_REQUIRE(h_rowptr[r] <= h_rowptr[r + 1], BLKAMG_EINVAL, "rowptr not monotone");
+    for (int32_t k = h_rowptr[r]; k < h_rowptr[r + 1]; ++k) {
+      BLK_REQUIRE(h_colidx[k] >= 0 && h_colidx[k] < n_nodes, BLKAMG_EINVAL, "column index out of range");
+      BLK_REQUIRE(k == h_rowptr[r] || h_colidx[k] > h_colidx[k - 1], BLKAMG_EINVAL,
+                  "column indices must be strictly ascending per row");
+    }
+  }
+  auto R = std::make_unique<sa_result_s>();
+  R->n_nodes = n_nodes;
+  R->n_agg = blk::aggregate_host(n_nodes, h_rowptr, h_colidx, h_dirichlet, nullptr, R->agg);
+  constexpr int bs = 3, nc = 6;
+  std::vector<double> Pt;
+  blk::tentative_host(n_nodes, bs, nc, R->agg, R->n_agg, blk::rigid_body_modes(n_nodes, h_coords), Pt, R->bc);
+  R->pt_rowptr.assign(static_cast<size_t>(n_nodes) + 1, 0);
+  for (int32_t i = 0; i < n_nodes; ++i) {
+    if (R->agg[i] >= 0) {
+      R->pt_colidx.push_back(R->agg[i]);
+      R->pt_val.insert(R->pt_val.end(), Pt.begin() + static_cast<size_t>(i) * bs * nc,
+                       Pt.begin() + static_cast<size_t>(i + 1) * bs * nc);
+    }
+    R->pt_rowptr[i + 1] = static_cast<int32_t>(R->pt_colidx.size());
+  }
+  const std::vector<int32_t> arp(h_rowptr, h_rowptr + n_nodes + 1), aci(h_colidx, h_colidx + h_rowptr[n_nodes]);
+  blk::structural_product_host(n_nodes, arp, aci, R->n_agg, R->pt_rowptr, R->pt_colidx, R->sp_rowptr, R->sp_colidx);
+  *out = R.release();
+  BLK_API_END
+}
+
+extern "C" int sa_result_info(sa_result_t r, int32_t* n_agg, int64_t* pt_nnzb, int64_t* sp_nnzb) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(r != nullptr, BLKAMG_EINVAL, "result is NULL");
+  if (n_agg) *n_agg = r->n_agg;
+  if (pt_nnzb) *pt_nnzb = static_cast<int64_t>(r->pt_colidx.size());
+  if (sp_nnzb) *sp_nnzb = static_cast<int64_t>(r->sp_colidx.size());
+  BLK_API_END
+}
+
+extern "C" int sa_result_arrays(sa_result_t r, const int32_t** agg, const int32_t** pt_rowptr,
+                                const int32_t** pt_colidx, const double** pt_val, const double** bc,
+                                const int32_t** sp_rowptr, const int32_t** sp_colidx) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(r != nullptr, BLKAMG_EINVAL, "result is NULL");
+  if (agg) *agg = r->agg.data();
+  if (pt_rowptr) *pt_rowptr = r->pt_rowptr.data();
+  if (pt_colidx) *pt_colidx = r->pt_colidx.data();
+  if (pt_val) *pt_val = r->pt_val.data();
+  if (bc) *bc = r->bc.data();
+  if (sp_rowptr) *sp_rowptr = r->sp_rowptr.data();
+  if (sp_colidx) *sp_colidx = r->sp_colidx.data();
+  BLK_API_END
+}
+
+extern "C" int sa_result_free(sa_result_t r) {
+  BLK_API_BEGIN
+  delete r;
   BLK_API_END
 }

@@ -90,3 +90,33 @@ def test_single_hip_runtime_after_import():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("n,seed", [(4, None), (5, 3), (8, 7)])
+def test_sa_setup_host_matches_oracle(n, seed):
+    """sa_setup_host: aggregates and both patterns bit-exact, tentative prolongator and
+    coarse near-null space within 1e-12 of the oracle's QR (same signs), P~ B_c = B on
+    aggregated rows."""
+    m, A = _mesh_operator(n, seed)
+    r = B.sa_setup_host(A.rowptr, A.colidx, m.coords, m.dirichlet)
+    agg, n_agg = sa.aggregate(sa.strength_graph(A, m.dirichlet), m.dirichlet)
+    assert r["n_agg"] == n_agg and np.array_equal(r["agg"], agg)
+    Bn = sa.rigid_body_modes(m.coords)
+    Pt, Bc = sa.tentative_prolongator(agg, n_agg, Bn)
+    assert np.array_equal(r["pt_rowptr"], Pt.rowptr) and np.array_equal(r["pt_colidx"], Pt.colidx)
+    assert np.abs(r["pt_val"] - Pt.val).max() <= 1e-12
+    assert np.abs(r["bc"] - Bc).max() <= 1e-12 * max(1.0, np.abs(Bc).max())
+    rows = np.nonzero(r["agg"] >= 0)[0]
+    assert np.abs(np.einsum("tij,tjk->tik", r["pt_val"], r["bc"][r["pt_colidx"]]) - Bn[rows]).max() <= 1e-12
+    rp, ci = S.structural_product(A.rowptr, A.colidx, A.nbr, A.nbc, Pt.rowptr, Pt.colidx, Pt.nbc)
+    assert np.array_equal(r["sp_rowptr"], rp) and np.array_equal(r["sp_colidx"], ci)
+
+
+def test_sa_setup_host_errors():
+    m, A = _mesh_operator(4)
+    with pytest.raises(B.BlkAmgError):
+        B.sa_setup_host(A.rowptr, A.colidx[::-1].copy(), m.coords)   # columns not ascending
+    bad = A.colidx.copy()
+    bad[0] = A.nbr
+    with pytest.raises(B.BlkAmgError):
+        B.sa_setup_host(A.rowptr, bad, m.coords)
