@@ -80,6 +80,23 @@ const char* blkamg_last_error(void);
 /* Library version as an integer (major*10000 + minor*100 + patch). */
 int blkamg_version(void);
 
+/* Device memory.  Every device buffer the library allocates (owned patterns and
+ * values, plans, hierarchy data, work vectors) comes from alloc_fn(bytes, ctx),
+ * which must return memory of the current device aligned to 256 bytes, or NULL
+ * (the calling entry point then fails with ENOMEM; a misaligned pointer is handed
+ * back to free_fn and the call fails with EINVAL).  free_fn(ptr, bytes, ctx) gets
+ * each buffer back with the size it was allocated with, after the library has
+ * synchronised the device (as hipFree would), so stream-ordered pools such as
+ * PyTorch's caching allocator may reuse it at once.  Both NULL: hipMalloc/hipFree
+ * (the default).  Exactly one NULL: EINVAL.  A buffer is returned to the routine
+ * that allocated it, so the allocator may be changed while handles are alive;
+ * ctx must stay valid until every buffer allocated with it has been freed.
+ * Pinned host staging (hipHostMalloc) is not routed.  Not to be called while
+ * another thread is inside the library. */
+typedef void* (*blkamg_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*blkamg_free_fn)(void* ptr, size_t bytes, void* ctx);
+int blkamg_set_allocator(blkamg_alloc_fn alloc_fn, blkamg_free_fn free_fn, void* ctx);
+
 /* ==========================================================================
  * Rectangular-block sparse matrix (paper §2.3, §2.4: independent row and column
  * block sizes; one int32 column index per block).
@@ -307,6 +324,30 @@ int amg_galerkin_recompute(amg_t M, void* stream);
  * Chebyshev coefficients and the coarsest Cholesky factor.  Returns ENOTSPD if the
  * factorisation meets a non-positive pivot (sync check at the end).  Sync. */
 int amg_smoother_refresh(amg_t M, const double* h_lambda, void* stream);
+
+/* Hierarchy from operators the caller already has (paper §2.1: the V-cycle needs
+ * the level operators, the prolongators and the smoother data; §3.1: the coarse
+ * operators may come from elsewhere, e.g. ptap_numeric).  A: n_levels handles,
+ * A[0] F64 with 3x3 blocks, A[l >= 1] F64 with 6x6 blocks, all square; P:
+ * n_levels - 1 handles (may be NULL when n_levels = 1), P[l] F64 with
+ * A[l].nbr x A[l+1].nbr block rows x columns and A[l].bs x 6 blocks.  The A
+ * handles are borrowed and must outlive the hierarchy; the P values and patterns
+ * are copied.  Computes the smoother data as amg_smoother_refresh does (block-
+ * diagonal inverses, lambda_hat by Lanczos or the learned model as opts.eig_mode
+ * says, Chebyshev coefficients, Cholesky factor of A[n_levels - 1]).  One instance;
+ * opts.hier_dtype must be F64 (EINVAL otherwise), opts may be NULL.  Such a
+ * hierarchy has no aggregates (amg_aggregates returns EINVAL) and
+ * amg_galerkin_recompute refuses it: the caller recomputes A[l >= 1] and then calls
+ * amg_hierarchy_update.  ENOTSPD if the coarsest factorisation fails.  Sync;
+ * allocates. */
+int amg_hierarchy_create(int32_t n_levels, const bsr_t* A, const bsr_t* P,
+                         const blkamg_opts* opts, void* stream, amg_t* out);
+/* Refresh the smoother data from the current level operators (paper §3.1; any
+ * hierarchy): as amg_smoother_refresh, with lambda_hat given in single precision,
+ * h_lambda float[n_levels - 1][n_inst] (level-major; entries of instances not
+ * smoothed on a level are ignored, the others must be positive, EINVAL otherwise),
+ * or computed by the configured estimator when h_lambda is NULL.  Sync. */
+int amg_hierarchy_update(amg_t M, const float* h_lambda, void* stream);
 
 /* One V-cycle from a zero guess, z = M^-1 r (paper §2.1): Chebyshev/point-block-
  * Jacobi pre-smoothing, residual, restriction with P^T, recursion, prolongation,

@@ -61,6 +61,7 @@ class Opts(C.Structure):
 _SIG = {
     "blkamg_last_error": (C.c_char_p, []),
     "blkamg_version": (C.c_int, []),
+    "blkamg_set_allocator": (C.c_int, [_p, _p, _p]),
     "bsr_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, _p, C.c_int, C.POINTER(_p)]),
     "bsr_destroy": (C.c_int, [_p]),
     "bsr_mark_modified": (C.c_int, [_p]),
@@ -93,6 +94,8 @@ _SIG = {
     "amg_lambdas": (C.c_int, [_p, _p]),
     "amg_galerkin_recompute": (C.c_int, [_p, _p]),
     "amg_smoother_refresh": (C.c_int, [_p, _p, _p]),
+    "amg_hierarchy_create": (C.c_int, [_i32, _p, _p, C.POINTER(Opts), _p, C.POINTER(_p)]),
+    "amg_hierarchy_update": (C.c_int, [_p, _p, _p]),
     "vcycle_apply": (C.c_int, [_p, _p, _p, _i32, _p]),
     "mlp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _i32, _i32, _p, _i32, _p, _i32, _p, _i32, _p]),
     "mlp_forward": (C.c_int, [_p, _p, _i32, _p, _p, _p, _p]),
@@ -438,12 +441,79 @@ def amg_galerkin_recompute(M: Amg, stream=None):
     _check(_lib.amg_galerkin_recompute(M.h, _stream(stream)), "amg_galerkin_recompute")
 
 
+def _lambda_arg(M: Amg, lambdas, dtype):
+    """Host array [n_levels - 1][n_inst] of `dtype` (kept alive by the caller) and its pointer."""
+    if lambdas is None:
+        return None, None
+    arr = np.ascontiguousarray(lambdas, dtype=dtype)
+    want = max(M.num_levels() - 1, 0) * M.num_instances()
+    if arr.size != want:
+        raise ValueError(f"lambdas has {arr.size} entries, the hierarchy needs {want}")
+    return arr, arr.ctypes.data_as(_p)
+
+
 def amg_smoother_refresh(M: Amg, lambdas=None, stream=None):
-    lam = None
-    if lambdas is not None:
-        lam_arr = np.ascontiguousarray(lambdas, dtype=np.float64)
-        lam = lam_arr.ctypes.data_as(_p)
+    arr, lam = _lambda_arg(M, lambdas, np.float64)
     _check(_lib.amg_smoother_refresh(M.h, lam, _stream(stream)), "amg_smoother_refresh")
+    del arr
+
+
+def amg_hierarchy_create(A: list, P: list, opts: Opts | None = None, stream=None) -> Amg:
+    """Hierarchy from caller operators A[0..L-1] (F64; 3x3 then 6x6 blocks) and prolongators
+    P[0..L-2] (F64, copied).  The A handles are kept alive by the returned object."""
+    n = len(A)
+    if len(P) != max(n - 1, 0):
+        raise ValueError("need len(P) == len(A) - 1")
+    a_arr = (_p * n)(*[x.h for x in A])
+    p_arr = (_p * max(n - 1, 1))(*([x.h for x in P] or [None]))
+    o = opts or blkamg_opts_default()
+    h = _p()
+    _check(_lib.amg_hierarchy_create(n, a_arr, p_arr if P else None, C.byref(o), _stream(stream), C.byref(h)),
+           "amg_hierarchy_create")
+    return Amg(h, keep=tuple(A))
+
+
+def amg_hierarchy_update(M: Amg, lambdas=None, stream=None):
+    """Smoother refresh with lambda_hat given in single precision ([n_levels - 1][n_inst]) or estimated."""
+    arr, lam = _lambda_arg(M, lambdas, np.float32)
+    _check(_lib.amg_hierarchy_update(M.h, lam, _stream(stream)), "amg_hierarchy_update")
+    del arr
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+_allocator_keep = []  # every callback pair ever installed: buffers return to the pair that made them
+
+
+def blkamg_set_allocator(alloc_fn=None, free_fn=None, ctx=None):
+    """Route the library's device allocations through alloc_fn(bytes, ctx) -> int pointer and
+    free_fn(ptr, bytes, ctx) (Python callables), or back to hipMalloc/hipFree when both are None."""
+    if alloc_fn is None and free_fn is None:
+        _check(_lib.blkamg_set_allocator(None, None, None), "blkamg_set_allocator")
+        return
+    a = _ALLOC_FN(alloc_fn) if alloc_fn is not None else None
+    f = _FREE_FN(free_fn) if free_fn is not None else None
+    _check(_lib.blkamg_set_allocator(C.cast(a, _p) if a else None, C.cast(f, _p) if f else None, ctx),
+           "blkamg_set_allocator")
+    _allocator_keep.append((a, f))
+
+
+def use_torch_allocator(enable=True):
+    """Take the library's device memory from PyTorch's caching allocator (current device and stream)."""
+    if not enable:
+        blkamg_set_allocator()
+        return
+
+    def alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def free(ptr, _nbytes, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    blkamg_set_allocator(alloc, free)
 
 
 def vcycle_apply(M: Amg, r, z, nrhs=1, stream=None):

@@ -106,6 +106,7 @@ struct amg_s {
   std::vector<int32_t> fallback;       // per level: 1 if the last refresh fell back to Lanczos
   std::vector<double> growth;          // [level][inst] A-norm growth of the smoother test
   std::vector<double> omega;           // [level][inst] predicted prolongator weight
+  bool user_ops = false;               // operators supplied by the caller (amg_hierarchy_create)
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -933,14 +934,7 @@ void autotune_hierarchy(amg_s* M, int nr, hipStream_t s) {
   }
 }
 
-amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double* h_coords,
-                  const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream) {
-  BLK_REQUIRE(A0 != nullptr && h_coords != nullptr, BLKAMG_EINVAL, "NULL argument");
-  blkamg_opts o;
-  if (opts) o = *opts; else blkamg_opts_default(&o);
-  BLK_REQUIRE(A0->dtype == BLKAMG_F64, BLKAMG_EINVAL, "A0 must be F64");
-  BLK_REQUIRE(A0->br == 3 && A0->bc == 3 && A0->nbr == A0->nbc, BLKAMG_EINVAL, "A0 must be square with 3x3 blocks");
-  BLK_REQUIRE(A0->nbr > 0, BLKAMG_EINVAL, "A0 is empty");
+void check_opts(const blkamg_opts& o) {
   BLK_REQUIRE(o.max_levels >= 1 && o.cheb_degree >= 1 && o.cheb_degree <= kMaxCheb, BLKAMG_EINVAL,
               "bad max_levels or cheb_degree");
   BLK_REQUIRE(o.lanczos_steps >= 2 && o.lanczos_steps <= kMaxLanczos, BLKAMG_EINVAL, "lanczos_steps must be in 2..64");
@@ -954,23 +948,13 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   BLK_REQUIRE(o.autotune_nrhs == 0 || o.autotune_nrhs == 1 || o.autotune_nrhs == 8, BLKAMG_EINVAL,
               "autotune_nrhs must be 0, 1 or 8");
   BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
-  BLK_REQUIRE(n_inst >= 1 && n_inst <= 65535, BLKAMG_EINVAL, "n_inst must be in 1..65535");
-  std::vector<int32_t> row0(static_cast<size_t>(n_inst) + 1);
-  if (h_row0) {
-    std::copy(h_row0, h_row0 + n_inst + 1, row0.begin());
-  } else {
-    BLK_REQUIRE(n_inst == 1, BLKAMG_EINVAL, "h_inst_row0 is required for n_inst > 1");
-    row0 = {0, A0->nbr};
-  }
-  BLK_REQUIRE(row0[0] == 0 && row0[n_inst] == A0->nbr, BLKAMG_EINVAL, "instance offsets must span A0's rows");
-  for (int t = 0; t < n_inst; ++t) BLK_REQUIRE(row0[t + 1] > row0[t], BLKAMG_EINVAL, "empty instance");
-  hipStream_t s = as_stream(stream);
-  HIP_CHECK(hipStreamSynchronize(s));
-  if (n_inst > 1) check_block_diagonal(A0, row0);
+}
 
+// The parts of a hierarchy that do not depend on how its levels were made.
+std::unique_ptr<amg_s> new_amg(const blkamg_opts& o, bsr_s* A0, int32_t n_inst, const std::vector<int32_t>& row0) {
   auto M = std::make_unique<amg_s>();
   M->o = o;
-  M->T = BLKAMG_F64;  // the cold setup runs in F64; an F32 hierarchy is derived at the end
+  M->T = BLKAMG_F64;  // an F32 hierarchy is derived from the F64 levels at the end of the setup
   M->A0 = A0;
   M->n_inst = n_inst;
   M->inst_row0 = row0;
@@ -985,6 +969,54 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&M->host_s), S_COUNT * sizeof(double)));
   HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&M->host_stat), 4 * sizeof(int32_t)));
   M->bstat.alloc(4);
+  return M;
+}
+
+// Dot grids of the batched CG, solver vectors, learned-part samples, smoother refresh
+// and (optionally) the lane autotuner, once the levels exist.
+void finish_setup(amg_s* M, hipStream_t s) {
+  {
+    std::vector<int64_t> doff;
+    std::vector<int32_t> d32;
+    for (int t = 0; t <= M->n_inst; ++t) {
+      doff.push_back(static_cast<int64_t>(M->inst_row0[t]) * M->A0->br);
+      d32.push_back(M->inst_row0[t] * M->A0->br);
+    }
+    build_grid(M, M->fgrid[0], doff, 4096, 1);
+    build_grid(M, M->fgrid[1], doff, 512, 8);
+    upload(M->d_fine_dof_off, d32);
+  }
+  ensure_vectors(M, 1);
+  map_samples(M);
+  smoother_refresh(M, nullptr, s);
+  if (M->o.autotune_nrhs > 0) autotune_hierarchy(M, M->o.autotune_nrhs, s);
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double* h_coords,
+                  const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream) {
+  BLK_REQUIRE(A0 != nullptr && h_coords != nullptr, BLKAMG_EINVAL, "NULL argument");
+  blkamg_opts o;
+  if (opts) o = *opts; else blkamg_opts_default(&o);
+  BLK_REQUIRE(A0->dtype == BLKAMG_F64, BLKAMG_EINVAL, "A0 must be F64");
+  BLK_REQUIRE(A0->br == 3 && A0->bc == 3 && A0->nbr == A0->nbc, BLKAMG_EINVAL, "A0 must be square with 3x3 blocks");
+  BLK_REQUIRE(A0->nbr > 0, BLKAMG_EINVAL, "A0 is empty");
+  check_opts(o);
+  BLK_REQUIRE(n_inst >= 1 && n_inst <= 65535, BLKAMG_EINVAL, "n_inst must be in 1..65535");
+  std::vector<int32_t> row0(static_cast<size_t>(n_inst) + 1);
+  if (h_row0) {
+    std::copy(h_row0, h_row0 + n_inst + 1, row0.begin());
+  } else {
+    BLK_REQUIRE(n_inst == 1, BLKAMG_EINVAL, "h_inst_row0 is required for n_inst > 1");
+    row0 = {0, A0->nbr};
+  }
+  BLK_REQUIRE(row0[0] == 0 && row0[n_inst] == A0->nbr, BLKAMG_EINVAL, "instance offsets must span A0's rows");
+  for (int t = 0; t < n_inst; ++t) BLK_REQUIRE(row0[t + 1] > row0[t], BLKAMG_EINVAL, "empty instance");
+  hipStream_t s = as_stream(stream);
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (n_inst > 1) check_block_diagonal(A0, row0);
+
+  auto M = new_amg(o, A0, n_inst, row0);
 
   // ---- cold setup in F64 ----
   const int nc_bs = 6;
@@ -1127,23 +1159,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     }
     M->T = BLKAMG_F32;
   }
-  // fine-level dot grids of the batched CG (all instances, 1 and 8 right-hand sides)
-  {
-    std::vector<int64_t> doff;
-    std::vector<int32_t> d32;
-    for (int t = 0; t <= n_inst; ++t) {
-      doff.push_back(static_cast<int64_t>(row0[t]) * 3);
-      d32.push_back(row0[t] * 3);
-    }
-    build_grid(M.get(), M->fgrid[0], doff, 4096, 1);
-    build_grid(M.get(), M->fgrid[1], doff, 512, 8);
-    upload(M->d_fine_dof_off, d32);
-  }
-  ensure_vectors(M.get(), 1);
-  map_samples(M.get());
-  smoother_refresh(M.get(), nullptr, s);
-  if (o.autotune_nrhs > 0) autotune_hierarchy(M.get(), o.autotune_nrhs, s);
-  HIP_CHECK(hipStreamSynchronize(s));
+  finish_setup(M.get(), s);
   return M.release();
 }
 
@@ -1493,6 +1509,7 @@ int amg_aggregates(amg_t M, int32_t level, int32_t* h_agg) {
   BLK_API_BEGIN
   Level* L = get_level(M, level);
   BLK_REQUIRE(L->n_act > 0, BLKAMG_EINVAL, "the level has no smoothed rows");
+  BLK_REQUIRE(!M->user_ops, BLKAMG_EINVAL, "no aggregates: the prolongators were supplied by the caller");
   BLK_REQUIRE(h_agg != nullptr, BLKAMG_EINVAL, "h_agg is NULL");
   std::copy(L->agg.begin(), L->agg.end(), h_agg);
   BLK_API_END
@@ -1514,7 +1531,77 @@ int amg_lambdas(amg_t M, double* h_lam) {
 int amg_galerkin_recompute(amg_t M, void* stream) {
   BLK_API_BEGIN
   BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  BLK_REQUIRE(!M->user_ops, BLKAMG_EINVAL,
+              "the coarse operators belong to the caller: recompute them with ptap_numeric, then amg_hierarchy_update");
   galerkin_recompute(M, as_stream(stream));
+  BLK_API_END
+}
+
+int amg_hierarchy_create(int32_t n_levels, const bsr_t* A, const bsr_t* P, const blkamg_opts* opts, void* stream,
+                         amg_t* out) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(out != nullptr && A != nullptr, BLKAMG_EINVAL, "NULL argument");
+  *out = nullptr;
+  blkamg_opts o;
+  if (opts) o = *opts; else blkamg_opts_default(&o);
+  check_opts(o);
+  BLK_REQUIRE(o.hier_dtype == BLKAMG_F64, BLKAMG_EINVAL, "caller-supplied operators are used in F64: hier_dtype must be F64");
+  BLK_REQUIRE(n_levels >= 1 && n_levels <= o.max_levels, BLKAMG_EINVAL, "n_levels must be in 1..max_levels");
+  BLK_REQUIRE(n_levels == 1 || P != nullptr, BLKAMG_EINVAL, "P is NULL");
+  for (int l = 0; l < n_levels; ++l) {
+    const bsr_s* a = A[l];
+    BLK_REQUIRE(a != nullptr && a->dtype == BLKAMG_F64 && a->br == a->bc && a->nbr == a->nbc && a->nbr > 0,
+                BLKAMG_EINVAL, "A[" + std::to_string(l) + "] must be a non-empty square-blocked F64 operator");
+    BLK_REQUIRE(l == 0 ? a->br == 3 : a->br == 6, BLKAMG_EINVAL,
+                "A[0] must have 3x3 blocks and coarser levels 6x6 blocks");
+    if (l + 1 < n_levels) {
+      const bsr_s* p = P[l];
+      BLK_REQUIRE(p != nullptr && p->dtype == BLKAMG_F64 && p->nbr == a->nbr && p->br == a->br && p->bc == 6 &&
+                      p->nbc == A[l + 1]->nbr,
+                  BLKAMG_EINVAL, "P[" + std::to_string(l) + "] must be F64, A[l].nbr x A[l+1].nbr, blocks bs x 6");
+    }
+  }
+  hipStream_t s = as_stream(stream);
+  HIP_CHECK(hipStreamSynchronize(s));
+  const std::vector<int32_t> row0{0, A[0]->nbr};
+  auto M = new_amg(o, A[0], 1, row0);
+  M->user_ops = true;
+  for (int l = 0; l < n_levels; ++l) {
+    auto L = std::make_unique<Level>();
+    L->A = A[l];
+    L->seg_inst = {0};
+    L->seg_off = {0, A[l]->nbr};
+    L->n_act = l + 1 < n_levels ? 1 : 0;
+    finalize_level(M.get(), *L);
+    if (l + 1 < n_levels) {
+      // the library keeps its own copy of the prolongator values and pattern
+      bsr_s* p = P[l];
+      ensure_host_pattern(p);
+      std::vector<int32_t> rp = p->h_rowptr, ci = p->h_colidx;
+      L->P = make_owned(p->nbr, p->nbc, p->br, p->bc, BLKAMG_F64, std::move(rp), std::move(ci));
+      HIP_CHECK(hipMemcpyAsync(L->P->val, p->val, p->val_bytes(), hipMemcpyDeviceToDevice, s));
+      L->n_agg = A[l + 1]->nbr;
+    }
+    M->lv.push_back(std::move(L));
+  }
+  finish_setup(M.get(), s);
+  *out = M.release();
+  BLK_API_END
+}
+
+int amg_hierarchy_update(amg_t M, const float* h_lambda, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  std::vector<double> lam;
+  if (h_lambda) {
+    lam.assign(h_lambda, h_lambda + (M->lv.size() > 0 ? M->lv.size() - 1 : 0) * M->n_inst);
+    for (size_t l = 0; l + 1 < M->lv.size(); ++l) {
+      const Level& L = *M->lv[l];
+      for (int t = 0; t < L.n_act; ++t)
+        BLK_REQUIRE(lam[l * M->n_inst + L.seg_inst[t]] > 0.0, BLKAMG_EINVAL, "lambda must be positive");
+    }
+  }
+  smoother_refresh(M, h_lambda ? lam.data() : nullptr, as_stream(stream));
   BLK_API_END
 }
 

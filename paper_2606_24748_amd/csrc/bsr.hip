@@ -318,6 +318,18 @@ const char* blkamg_last_error(void) { return g_last_error.c_str(); }
 
 int blkamg_version(void) { return 100; }
 
+int blkamg_set_allocator(blkamg_alloc_fn alloc_fn, blkamg_free_fn free_fn, void* ctx) {
+  BLK_API_BEGIN
+  BLK_REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), BLKAMG_EINVAL,
+              "alloc_fn and free_fn must both be set or both be NULL");
+  std::lock_guard<std::mutex> g(allocator_mutex());
+  DeviceAllocator& a = allocator_slot();
+  a.alloc_fn = alloc_fn;
+  a.free_fn = free_fn;
+  a.ctx = alloc_fn ? ctx : nullptr;
+  BLK_API_END
+}
+
 int bsr_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t nnzb, const int32_t* d_rowptr,
                const int32_t* d_colidx, void* d_val, int dtype, bsr_t* out) {
   BLK_API_BEGIN

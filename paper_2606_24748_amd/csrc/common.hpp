@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -61,36 +62,79 @@ void set_last_error(const std::string& msg);
   }
 
 // ---------------------------------------------------------------------------
-// Device buffer (owning, hipMalloc'd, freed on destruction)
+// Device allocator: hipMalloc/hipFree, or the caller's pair of routines
+// ---------------------------------------------------------------------------
+struct DeviceAllocator {
+  blkamg_alloc_fn alloc_fn = nullptr;  // NULL: hipMalloc / hipFree
+  blkamg_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+};
+inline std::mutex& allocator_mutex() {
+  static std::mutex m;
+  return m;
+}
+inline DeviceAllocator& allocator_slot() {
+  static DeviceAllocator a;
+  return a;
+}
+inline DeviceAllocator current_allocator() {
+  std::lock_guard<std::mutex> g(allocator_mutex());
+  return allocator_slot();
+}
+constexpr uintptr_t kDevAlign = 256;
+
+// ---------------------------------------------------------------------------
+// Device buffer (owning, freed on destruction by the routine that allocated it)
 // ---------------------------------------------------------------------------
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  DeviceAllocator by;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), by(o.by) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; by = o.by; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
     if (count == 0) return;
+    const size_t bytes = count * sizeof(T);
+    const DeviceAllocator a = current_allocator();
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(BLKAMG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    if (a.alloc_fn) {
+      q = a.alloc_fn(bytes, a.ctx);
+      if (q == nullptr) fail(BLKAMG_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+      if (reinterpret_cast<uintptr_t>(q) % kDevAlign != 0) {
+        a.free_fn(q, bytes, a.ctx);
+        fail(BLKAMG_EINVAL, "the caller's allocator returned a pointer not aligned to 256 bytes");
+      }
+    } else {
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(BLKAMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
     }
     p = static_cast<T*>(q);
     n = count;
+    by = a;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (by.free_fn) {
+        // as hipFree does: nothing queued may still use the buffer when it is handed back
+        (void)hipDeviceSynchronize();
+        by.free_fn(p, n * sizeof(T), by.ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = 0;
   }

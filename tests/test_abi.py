@@ -18,6 +18,7 @@ B = pytest.importorskip("paper_2606_24748_amd.blkamg", reason="libblkamg.so not 
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "blkamg.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"^\s*typedef[^;]*;", "", text, flags=re.M | re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
                        text, flags=re.M)
     return sorted(set(names) - {"if", "while"})
@@ -120,3 +121,14 @@ def test_sa_setup_host_errors():
     bad[0] = A.nbr
     with pytest.raises(B.BlkAmgError):
         B.sa_setup_host(A.rowptr, bad, m.coords)
+
+
+def test_set_allocator_arguments():
+    """Exactly one callback is an error; both or neither are accepted (no device work)."""
+    with pytest.raises(B.BlkAmgError) as e:
+        B.blkamg_set_allocator(lambda n, c: None, None)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BlkAmgError):
+        B.blkamg_set_allocator(None, lambda p, n, c: None)
+    B.blkamg_set_allocator(lambda n, c: None, lambda p, n, c: None)
+    B.blkamg_set_allocator()
