@@ -20,7 +20,10 @@ reported beside it.
 
 Also reported: the HBM roofline of the fine 3x3 FP64 SpMV (bsr_spmv) measured with
 HIP events, the Galerkin recompute's algorithmic bandwidth, and the CPU oracle timed
-on this host on a bounded sample (see cpu_baseline.sample).
+on this host on a bounded sample (see cpu_baseline.sample).  Side sections (not the
+value): the learned eigenbound at 96^3, a batch of 24 instances with 8 right-hand
+sides, and the triquadratic (Q2, 27-node) problem at 64^3 elements, which has the
+same dofs as the Q1 workload but about 2.4 times the blocks.
 """
 from __future__ import annotations
 
@@ -85,7 +88,9 @@ def parse_args(argv=None):
                     help="only assemble the fine operator and run the SpMV probe and the copy calibration")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-eigenbound section")
-    ap.add_argument("--only-section", choices=("learned", "batch"), default=None,
+    ap.add_argument("--no-q2", action="store_true", help="skip the triquadratic (Q2) section")
+    ap.add_argument("--q2-n", type=int, default=64, help="elements per edge of the Q2 problem")
+    ap.add_argument("--only-section", choices=("learned", "batch", "q2"), default=None,
                     help="run only that section and print its result (profiling runs)")
     ap.add_argument("--learned-n", type=int, default=96, help="edge of the learned-eigenbound deployment problem")
     ap.add_argument("--model", default=None, help="eigenbound model JSON (default: the packaged one)")
@@ -256,6 +261,44 @@ def run_batch(args, B, torch, dev, stream):
     return res
 
 
+def run_q2(args, B, RL, torch, dev, stream):
+    """Triquadratic (Q2, 27-node) elasticity at q2_n^3 elements: as many dofs as the Q1
+    problem with twice the edge (64^3 Q2 and 128^3 Q1 both have 6,440,067 dofs), with
+    block rows of 27 to 125 blocks instead of at most 27 (the nonzeros-per-row study of
+    paper §5, Table 4).  Same material and right-hand-side seeds and the same hot path
+    as the Q1 workload; mixed and FP64 hierarchies, then the fine FP64 SpMV probe."""
+    import synth
+
+    n = args.q2_n
+    t0 = time.perf_counter()
+    mesh = synth.make_mesh_q2(n)
+    ii, jj = synth.coo_indices(mesh)
+    mats = [synth.lame(*synth.materials(mesh.n_elem, 11)), synth.lame(*synth.materials(mesh.n_elem, 1011))]
+    vals = [synth.coo_values_torch(mesh, lam, mu, dev) for lam, mu in mats]
+    b = torch.as_tensor(synth.rhs(mesh, 12), device=dev)
+    log(f"[q2] inputs ready: n={n} dofs={mesh.n_dof} n_coo={len(ii)} ({time.perf_counter() - t0:.1f}s)")
+    t0 = time.perf_counter()
+    plan, HA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, ii, jj)
+    t_plan = time.perf_counter() - t0
+    del ii, jj
+    a_inf = HA.info()
+    log(f"[q2] coo plan: nnzb={a_inf['nnzb']} ({t_plan:.1f}s)")
+    res = {"n": n, "dofs": mesh.n_dof, "fine_nnzb": a_inf["nnzb"],
+           "scalar_nnz_per_row": a_inf["nnzb"] * 9 / mesh.n_dof, "coo_plan_s": t_plan}
+    for var in ("mixed", "fp64"):
+        r = run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b, tag=f"q2/{var}")
+        r.pop("_x", None)
+        res[var] = r
+    probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+    probe["frac"] = probe["achieved_GBs"] / RL.HBM_PEAK_GBS
+    res["spmv"] = probe
+    log(f"[q2] fine SpMV {probe['avg_launch_ms']:.3f} ms, {probe['achieved_GBs']:.0f} GB/s "
+        f"({100 * probe['frac']:.1f}% of HBM peak); mixed PCG+PtAP {res['mixed']['pcg_plus_ptap_s']:.4f} s")
+    del plan, HA, vals
+    torch.cuda.synchronize()
+    return res
+
+
 def run_learned(args, B, torch, dev, stream):
     """Deployment of the learned eigenbound on Q1 elasticity at learned_n^3 elements
     (material seed 21, redraw 1021, right-hand side seed 22): FP32 hierarchy with
@@ -329,6 +372,98 @@ def run_learned(args, B, torch, dev, stream):
     return res
 
 
+def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b, tag=None):
+    """Set up one hierarchy variant on the assembled operator and time the hot path
+    (assembly, Galerkin recompute, refresh, PCG) over warmup + steps passes."""
+    tag = tag or var
+    o = B.blkamg_opts_default()
+    if var == "fp64":
+        o.hier_dtype, o.p_dtype = B.F64, B.F64
+    elif var == "mixed":
+        o.hier_dtype, o.p_dtype = B.F32, B.F32
+    elif var == "mixed-mlp":
+        o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, B.EIG_MLP
+    elif var == "mixed-bf16":
+        o.hier_dtype, o.p_dtype = B.F32, B.BF16
+    else:
+        raise SystemExit(f"unknown variant {var}")
+    B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
+    t_setup = time.perf_counter() - t0
+    if var == "mixed-mlp":
+        from paper_2606_24748_amd import train_eigmlp
+        B.amg_set_eig_model(M, train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL))
+    nl = M.num_levels()
+    lev = []
+    for l in range(nl):
+        Al, Pl = M.level(l)
+        ai = Al.info()
+        lev.append({"nbr": ai["nbr"], "bs": ai["bs_r"], "nnzb": ai["nnzb"],
+                    "p_nnzb": Pl.info()["nnzb"] if Pl is not None else 0})
+    log(f"[{tag}] setup {t_setup:.1f}s levels {[(d['nbr'] * d['bs'], d['nnzb']) for d in lev]}")
+    x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev)
+    rec = []
+    for s in range(args.warmup + args.steps):
+        timed = s >= args.warmup
+        if s == args.warmup:
+            torch.cuda.synchronize()
+            t_region = time.perf_counter()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        vi = (s + 1) % 2
+        ev[0].record(stream)
+        B.coo_assemble_blocked(plan, vals[vi], B.INSERT, HA)
+        ev[1].record(stream)
+        B.amg_galerkin_recompute(M)
+        ev[2].record(stream)
+        B.amg_smoother_refresh(M)
+        ev[3].record(stream)
+        code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000)
+        ev[4].record(stream)
+        ev[4].synchronize()
+        ph = [ev[k].elapsed_time(ev[k + 1]) for k in range(4)]
+        if timed:
+            rec.append({"coo_ms": ph[0], "ptap_ms": ph[1], "refresh_ms": ph[2], "pcg_ms": ph[3], "its": its,
+                        "relres": rel, "status": code, "values": vi})
+        log(f"[{tag}] step {s} {'timed' if timed else 'warmup'}: coo {ph[0]:.2f} ms, ptap {ph[1]:.2f} ms, "
+            f"refresh {ph[2]:.2f} ms, pcg {ph[3]:.1f} ms ({its} its, relres {rel:.2e})")
+    torch.cuda.synchronize()
+    region_s = time.perf_counter() - t_region
+    # true residual of the last solve with the FP64 fine operator (library SpMV)
+    r = b.clone()
+    B.bsr_spmv(HA, -1.0, x, 1.0, r)
+    true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    med = {k: statistics.median(rr[k] for rr in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
+    # Galerkin recompute algorithmic bytes over all levels
+    vsz = 8 if o.hier_dtype == B.F64 else 4
+    psz = {B.F64: 8, B.F32: 4, B.BF16: 2}[o.p_dtype]
+    ptap_bytes = 0
+    for l in range(nl - 1):
+        d, c = lev[l], lev[l + 1]
+        ptap_bytes += RL.ptap_bytes(d["nbr"], d["nnzb"], d["bs"], d["p_nnzb"], 6, c["nbr"], c["nnzb"], vsz, psz)
+    if o.hier_dtype != B.F64:
+        ptap_bytes += a_inf["nnzb"] * 9 * (8 + 4)  # cast of the fine operator to the F32 copy
+    res = {
+        "setup_s": t_setup, "levels": lev, "steps": rec, "median_ms": med,
+        "pcg_plus_ptap_s": (med["pcg_ms"] + med["ptap_ms"]) / 1e3,
+        "ms_per_step": region_s * 1e3 / max(args.steps, 1),
+        "iterations": [rr["its"] for rr in rec], "true_relres": true_rel,
+        "ptap_alg_GBs": ptap_bytes / (med["ptap_ms"] * 1e-3) / 1e9,
+        "ptap_alg_bytes": ptap_bytes,
+        "x_norm": float(torch.linalg.norm(x)),
+    }
+    res["_x"] = x
+    res["lambdas"] = M.lambdas().tolist()
+    if var == "mixed-mlp":
+        fb, g, _ = B.amg_eig_status(M)
+        res["fallback_levels"] = fb.tolist()
+        res["growth"] = g[:, 0].tolist()
+    del M
+    torch.cuda.synchronize()
+    return res
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.cpu_baseline_only:
@@ -350,8 +485,12 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     if args.only_section:
         stream = torch.cuda.current_stream()
-        run = run_learned if args.only_section == "learned" else run_batch
-        print(json.dumps({"section": args.only_section, "result": run(args, B, torch, dev, stream)}))
+        if args.only_section == "q2":
+            result = run_q2(args, B, RL, torch, dev, stream)
+        else:
+            run = run_learned if args.only_section == "learned" else run_batch
+            result = run(args, B, torch, dev, stream)
+        print(json.dumps({"section": args.only_section, "result": result}))
         return 0
     n = args.n
     t_all = time.perf_counter()
@@ -378,97 +517,17 @@ def main(argv=None):
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     results = {}
     for var in variants:
-        o = B.blkamg_opts_default()
-        if var == "fp64":
-            o.hier_dtype, o.p_dtype = B.F64, B.F64
-        elif var == "mixed":
-            o.hier_dtype, o.p_dtype = B.F32, B.F32
-        elif var == "mixed-mlp":
-            o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, B.EIG_MLP
-        elif var == "mixed-bf16":
-            o.hier_dtype, o.p_dtype = B.F32, B.BF16
-        else:
-            raise SystemExit(f"unknown variant {var}")
-        B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
-        t_setup = time.perf_counter() - t0
-        if var == "mixed-mlp":
-            from paper_2606_24748_amd import train_eigmlp
-            B.amg_set_eig_model(M, train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL))
-        nl = M.num_levels()
-        lev = []
-        for l in range(nl):
-            Al, Pl = M.level(l)
-            ai = Al.info()
-            lev.append({"nbr": ai["nbr"], "bs": ai["bs_r"], "nnzb": ai["nnzb"],
-                        "p_nnzb": Pl.info()["nnzb"] if Pl is not None else 0})
-        log(f"[{var}] setup {t_setup:.1f}s levels {[(d['nbr'] * d['bs'], d['nnzb']) for d in lev]}")
-        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev)
-        rec = []
-        for s in range(args.warmup + args.steps):
-            timed = s >= args.warmup
-            if s == args.warmup:
-                torch.cuda.synchronize()
-                t_region = time.perf_counter()
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-            vi = (s + 1) % 2
-            ev[0].record(stream)
-            B.coo_assemble_blocked(plan, vals[vi], B.INSERT, HA)
-            ev[1].record(stream)
-            B.amg_galerkin_recompute(M)
-            ev[2].record(stream)
-            B.amg_smoother_refresh(M)
-            ev[3].record(stream)
-            code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000)
-            ev[4].record(stream)
-            ev[4].synchronize()
-            ph = [ev[k].elapsed_time(ev[k + 1]) for k in range(4)]
-            if timed:
-                rec.append({"coo_ms": ph[0], "ptap_ms": ph[1], "refresh_ms": ph[2], "pcg_ms": ph[3], "its": its,
-                            "relres": rel, "status": code, "values": vi})
-            log(f"[{var}] step {s} {'timed' if timed else 'warmup'}: coo {ph[0]:.2f} ms, ptap {ph[1]:.2f} ms, "
-                f"refresh {ph[2]:.2f} ms, pcg {ph[3]:.1f} ms ({its} its, relres {rel:.2e})")
-        torch.cuda.synchronize()
-        region_s = time.perf_counter() - t_region
-        # true residual of the last solve with the FP64 fine operator (library SpMV)
-        r = b.clone()
-        B.bsr_spmv(HA, -1.0, x, 1.0, r)
-        true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
-        med = {k: statistics.median(rr[k] for rr in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
-        # Galerkin recompute algorithmic bytes over all levels
-        vsz = 8 if o.hier_dtype == B.F64 else 4
-        psz = {B.F64: 8, B.F32: 4, B.BF16: 2}[o.p_dtype]
-        ptap_bytes = 0
-        for l in range(nl - 1):
-            d, c = lev[l], lev[l + 1]
-            ptap_bytes += RL.ptap_bytes(d["nbr"], d["nnzb"], d["bs"], d["p_nnzb"], 6, c["nbr"], c["nnzb"], vsz, psz)
-        if o.hier_dtype != B.F64:
-            ptap_bytes += a_inf["nnzb"] * 9 * (8 + 4)  # cast of the fine operator to the F32 copy
-        results[var] = {
-            "setup_s": t_setup, "levels": lev, "steps": rec, "median_ms": med,
-            "pcg_plus_ptap_s": (med["pcg_ms"] + med["ptap_ms"]) / 1e3,
-            "ms_per_step": region_s * 1e3 / max(args.steps, 1),
-            "iterations": [rr["its"] for rr in rec], "true_relres": true_rel,
-            "ptap_alg_GBs": ptap_bytes / (med["ptap_ms"] * 1e-3) / 1e9,
-            "ptap_alg_bytes": ptap_bytes,
-            "x_norm": float(torch.linalg.norm(x)),
-        }
-        results[var]["_x"] = x
-        results[var]["lambdas"] = M.lambdas().tolist()
-        if var == "mixed-mlp":
-            fb, g, _ = B.amg_eig_status(M)
-            results[var]["fallback_levels"] = fb.tolist()
-            results[var]["growth"] = g[:, 0].tolist()
-        del M
-        torch.cuda.synchronize()
+        results[var] = run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b)
 
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
     batch = None
     learned = None
+    q2 = None
     del plan, HA, vals
     torch.cuda.empty_cache()
+    if not args.no_q2:
+        q2 = run_q2(args, B, RL, torch, dev, stream)
+        torch.cuda.empty_cache()
     if not args.no_learned:
         learned = run_learned(args, B, torch, dev, stream)
         torch.cuda.empty_cache()
@@ -510,6 +569,7 @@ def main(argv=None):
         "variants": results,
         "batch": batch,
         "learned": learned,
+        "q2": q2,
         "coo_plan_s": t_plan,
     }
     if "fp64" in results and head != "fp64":

@@ -40,7 +40,12 @@ class Q1Mesh:
     n_elem: int
     coords: np.ndarray      # [n_nodes, 3] float64
     dirichlet: np.ndarray   # [n_nodes] bool
-    elem_nodes: np.ndarray  # [n_elem, 8] int64, local order above
+    elem_nodes: np.ndarray  # [n_elem, npe] int64, local order above (Q2: synth.q2)
+    order: int = 1          # 1 trilinear (8 nodes), 2 triquadratic (27 nodes)
+
+    @property
+    def npe(self) -> int:
+        return self.elem_nodes.shape[1]
 
     @property
     def n_dof(self) -> int:
@@ -48,6 +53,7 @@ class Q1Mesh:
 
     @property
     def h(self) -> float:
+        """Element side (the Q2 lattice spacing is h/2)."""
         return 1.0 / self.n
 
     @property
@@ -113,17 +119,21 @@ def reference_element_matrices() -> tuple[np.ndarray, np.ndarray]:
     return Kl.reshape(24, 24), Km.reshape(24, 24)
 
 
-_REF = None
+_REF = {}
 
 
-def _ref_blocks() -> tuple[np.ndarray, np.ndarray]:
-    """Reference matrices split into [8, 8, 3, 3] node blocks."""
-    global _REF
-    if _REF is None:
-        Kl, Km = reference_element_matrices()
-        _REF = (Kl.reshape(8, 3, 8, 3).transpose(0, 2, 1, 3).copy(),
-                Km.reshape(8, 3, 8, 3).transpose(0, 2, 1, 3).copy())
-    return _REF
+def _ref_blocks(order: int = 1) -> tuple[np.ndarray, np.ndarray]:
+    """Reference matrices of the element of `order` split into [npe, npe, 3, 3] node blocks."""
+    if order not in _REF:
+        if order == 1:
+            Kl, Km = reference_element_matrices()
+        else:
+            from .q2 import reference_element_matrices_q2
+            Kl, Km = reference_element_matrices_q2()
+        k = Kl.shape[0] // 3
+        _REF[order] = (Kl.reshape(k, 3, k, 3).transpose(0, 2, 1, 3).copy(),
+                       Km.reshape(k, 3, k, 3).transpose(0, 2, 1, 3).copy())
+    return _REF[order]
 
 
 def lame(E, nu):
@@ -153,23 +163,26 @@ def homogeneous_materials(n_elem: int, E: float = 1.0, nu: float = 0.3):
     return np.full(n_elem, E), np.full(n_elem, nu)
 
 
-def stream_sizes(n: int, clamp: bool = True) -> dict:
-    m = n + 1
+def stream_sizes(n: int, clamp: bool = True, order: int = 1) -> dict:
+    m = order * n + 1
+    npe = (order + 1) ** 3
     n_dir = m * m if clamp else 0
     return {"n_nodes": m ** 3, "n_dof": 3 * m ** 3, "n_elem": n ** 3,
-            "n_dirichlet": n_dir, "n_coo": 64 * n ** 3 + n_dir}
+            "n_dirichlet": n_dir, "n_coo": npe * npe * n ** 3 + n_dir}
 
 
 def coo_indices(mesh: Q1Mesh) -> tuple[np.ndarray, np.ndarray]:
-    """Block coordinates (i, j) of the element stream, int32, length 64*n_elem + n_dir.
+    """Block coordinates (i, j) of the element stream, int32, length npe^2*n_elem + n_dir
+    (npe = 8 nodes per element for Q1, 27 for Q2).
 
-    Entry 64*e + 8*a + b couples local nodes a (row) and b (column) of element e;
+    Entry npe^2*e + npe*a + b couples local nodes a (row) and b (column) of element e;
     it is (-1, -1) if either node is Dirichlet.  The last n_dir entries are the
     diagonal blocks (d, d) of the Dirichlet nodes in ascending order.
     """
     en = mesh.elem_nodes.astype(np.int32)
-    ii = np.repeat(en, 8, axis=1)          # [e, 8a+b] -> node a
-    jj = np.tile(en, (1, 8))               # [e, 8a+b] -> node b
+    k = mesh.npe
+    ii = np.repeat(en, k, axis=1)          # [e, k*a+b] -> node a
+    jj = np.tile(en, (1, k))               # [e, k*a+b] -> node b
     dmask = mesh.dirichlet
     drop = dmask[ii] | dmask[jj]
     ii[drop] = -1
@@ -180,16 +193,17 @@ def coo_indices(mesh: Q1Mesh) -> tuple[np.ndarray, np.ndarray]:
 
 def coo_values(mesh: Q1Mesh, lam: np.ndarray, mu: np.ndarray, dtype=np.float64) -> np.ndarray:
     """Block values [n_coo, 3, 3] matching `coo_indices` (host numpy)."""
-    KlB, KmB = _ref_blocks()
+    KlB, KmB = _ref_blocks(mesh.order)
     h = mesh.h
     ne = mesh.n_elem
-    out = np.empty((64 * ne + mesh.n_dirichlet, 3, 3), dtype=dtype)
-    ev = out[: 64 * ne].reshape(ne, 8, 8, 3, 3)
-    chunk = 1 << 16
+    k = mesh.npe
+    out = np.empty((k * k * ne + mesh.n_dirichlet, 3, 3), dtype=dtype)
+    ev = out[: k * k * ne].reshape(ne, k, k, 3, 3)
+    chunk = max(1, (1 << 22) // (k * k))
     for s in range(0, ne, chunk):
         e = slice(s, min(ne, s + chunk))
         ev[e] = h * (lam[e, None, None, None, None] * KlB[None] + mu[e, None, None, None, None] * KmB[None])
-    out[64 * ne:] = np.eye(3)
+    out[k * k * ne:] = np.eye(3)
     return out
 
 
@@ -198,21 +212,22 @@ def coo_values_torch(mesh: Q1Mesh, lam, mu, device, dtype=None):
     (input generation for large problems; no solver arithmetic)."""
     import torch
     dtype = dtype or torch.float64
-    KlB, KmB = _ref_blocks()
+    KlB, KmB = _ref_blocks(mesh.order)
     h = mesh.h
     ne = mesh.n_elem
-    out = torch.empty((64 * ne + mesh.n_dirichlet, 3, 3), dtype=dtype, device=device)
+    k = mesh.npe
+    out = torch.empty((k * k * ne + mesh.n_dirichlet, 3, 3), dtype=dtype, device=device)
     kl = torch.as_tensor(KlB * h, dtype=torch.float64, device=device)
     km = torch.as_tensor(KmB * h, dtype=torch.float64, device=device)
     lam_t = torch.as_tensor(np.asarray(lam), dtype=torch.float64, device=device)
     mu_t = torch.as_tensor(np.asarray(mu), dtype=torch.float64, device=device)
-    ev = out[: 64 * ne].view(ne, 8, 8, 3, 3)
-    chunk = 1 << 18
+    ev = out[: k * k * ne].view(ne, k, k, 3, 3)
+    chunk = max(1, (1 << 24) // (k * k))
     for s in range(0, ne, chunk):
         e = slice(s, min(ne, s + chunk))
         ev[e] = (lam_t[e, None, None, None, None] * kl[None]
                  + mu_t[e, None, None, None, None] * km[None]).to(dtype)
-    out[64 * ne:] = torch.eye(3, dtype=dtype, device=device)
+    out[k * k * ne:] = torch.eye(3, dtype=dtype, device=device)
     return out
 
 

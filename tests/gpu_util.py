@@ -37,9 +37,9 @@ def rel2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def q1_problem(n, mat_seed=None):
-    """Mesh, oracle operator, and the stream that produced it."""
-    m = synth.make_mesh(n)
+def q1_problem(n, mat_seed=None, order=1):
+    """Mesh (trilinear, or triquadratic for order 2), oracle operator, and the stream that produced it."""
+    m = synth.make_mesh(n) if order == 1 else synth.make_mesh_q2(n)
     i, j = synth.coo_indices(m)
     if mat_seed is None:
         E, nu = synth.homogeneous_materials(m.n_elem)

@@ -1,0 +1,100 @@
+"""GPU parity on the triquadratic (Q2, 27-node) elasticity problem: block rows of 27 to
+125 blocks instead of at most 27 (the nonzeros-per-row study of paper §5, Table 4)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import sparse as S  # noqa: E402
+from oracle import solve  # noqa: E402
+from paper_2606_24748_amd import blkamg as B  # noqa: E402
+from tests.gpu_util import dev, from_device_bsr, q1_problem, rel2  # noqa: E402
+
+
+def _q2(n, seed, hier=B.F64, pdt=B.F64):
+    m, i, j, v, A = q1_problem(n, seed, order=2)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    o = B.blkamg_opts_default()
+    o.hier_dtype = hier
+    o.p_dtype = pdt
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    return m, i, j, A, plan, HA, M
+
+
+def test_q2_assembly_and_spmv_match_oracle():
+    m, i, j, v, A = q1_problem(5, 2, order=2)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    G = from_device_bsr(HA)
+    assert np.array_equal(G.rowptr, A.rowptr) and np.array_equal(G.colidx, A.colidx)
+    assert np.array_equal(G.val, A.val)
+    x = np.random.default_rng(1).uniform(-1, 1, (m.n_dof, 8))
+    for nrhs in (1, 8):
+        xs = x[:, 0].copy() if nrhs == 1 else x
+        y = torch.zeros(xs.shape, dtype=torch.float64, device="cuda")
+        B.bsr_spmv(HA, 1.0, dev(xs), 0.0, y, nrhs=nrhs)
+        want = S.spmv(A, xs) if nrhs == 1 else np.stack([S.spmv(A, xs[:, q]) for q in range(8)], axis=1)
+        assert rel2(y.cpu().numpy(), want) <= 1e-13
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (12, 3)])
+def test_q2_setup_matches_oracle(n, seed):
+    print(f"q2 setup n={n}", flush=True)
+    m, i, j, A, plan, HA, M = _q2(n, seed)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    assert M.num_levels() == H.n_levels
+    lam = M.lambdas()
+    for l in range(H.n_levels - 1):
+        L = H.levels[l]
+        assert np.array_equal(M.aggregates(l), L.agg)
+        assert abs(lam[l] - L.lam) <= 1e-12 * L.lam
+        P = from_device_bsr(M.level(l)[1])
+        assert np.array_equal(P.rowptr, L.P.rowptr) and np.array_equal(P.colidx, L.P.colidx)
+        assert rel2(P.val, L.P.val) <= 1e-12
+        Ac = from_device_bsr(M.level(l + 1)[0])
+        want = H.levels[l + 1].A
+        assert np.array_equal(Ac.rowptr, want.rowptr) and np.array_equal(Ac.colidx, want.colidx)
+        assert rel2(Ac.val, want.val) <= 1e-12
+
+
+def test_q2_vcycle_pcg_and_recompute_match_oracle():
+    m, i, j, A, plan, HA, M = _q2(12, 5)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    assert H.n_levels >= 3
+    r = np.random.default_rng(0).uniform(-1, 1, m.n_dof)
+    z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, dev(r), z)
+    assert rel2(z.cpu().numpy(), solve.vcycle(H, r)) <= 1e-11
+    b = synth.rhs(m, 2)
+    _, it_o, _, ok = solve.pcg(A, b, lambda q: solve.vcycle(H, q), rtol=1e-8)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
+    assert ok and code == B.OK and abs(it - it_o) <= 1
+    assert np.linalg.norm(b - S.spmv(A, x.cpu().numpy())) <= 2e-8 * np.linalg.norm(b)
+    # hot recompute with new materials on the fixed patterns
+    lam2, mu2 = synth.lame(*synth.materials(m.n_elem, 1005))
+    v2 = synth.coo_values(m, lam2, mu2)
+    B.coo_assemble_blocked(plan, dev(v2), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    B.amg_smoother_refresh(M)
+    H2 = solve.recompute(H, S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v2))
+    lam = M.lambdas()
+    for l in range(H2.n_levels - 1):
+        assert abs(lam[l] - H2.levels[l].lam) <= 1e-12 * H2.levels[l].lam
+        assert rel2(from_device_bsr(M.level(l + 1)[0]).val, H2.levels[l + 1].A.val) <= 1e-12
+
+
+@pytest.mark.parametrize("pdt", [B.F32, B.BF16])
+def test_q2_f32_hierarchy_converges(pdt):
+    m, i, j, A, plan, HA, M = _q2(12, 5, B.F32, pdt)
+    H = solve.setup(A, m.coords, m.dirichlet)
+    b = synth.rhs(m, 2)
+    _, it_o, _, _ = solve.pcg(A, b, lambda q: solve.vcycle(H, q), rtol=1e-8)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
+    assert code == B.OK and it <= it_o + 3
+    assert np.linalg.norm(b - S.spmv(A, x.cpu().numpy())) <= 2e-8 * np.linalg.norm(b)
