@@ -46,9 +46,9 @@ METRIC = "PCG solve s + PtAP recompute s at 128^3 elasticity; %HBM peak; mixed v
 # the kernel sources it was measured on (their SHA-256 below), else reported as null.
 # Summary and commands: profiles/bsr_spmv_fine_f64_128cube.md.
 TRAFFIC_RECORD = {
-    "sources_sha256": "82c1bedc7c31edf115c33d1a4f5d78d990126f69df63501666bb3441a509b097",
-    "fetch_bytes": 4505174016,   # FETCH_SIZE 2,199,792 KiB x 2.00 (copy calibration)
-    "write_bytes": 52819968,     # WRITE_SIZE 51,582 KiB x 1.00
+    "sources_sha256": "580dd93f827400b9603b6cdfa1e31be4c60798ecefc42d2d946939dde98b508f",
+    "fetch_bytes": 4505270272,   # FETCH_SIZE 2,199,839 KiB x 2.00 (copy calibration)
+    "write_bytes": 52825088,     # WRITE_SIZE 51,587 KiB x 1.00
 }
 TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_amd/csrc/bsr.hip",
                    "paper_2606_24748_amd/csrc/common.hpp")
