@@ -61,9 +61,12 @@ class Q1Mesh:
         return int(self.dirichlet.sum())
 
 
-def make_mesh(n: int, clamp: bool = True) -> Q1Mesh:
+def make_mesh(n: int, clamp: bool = True, distort: float = 0.0, seed: int = 0) -> Q1Mesh:
     """Structured n^3-element mesh of the unit cube; `clamp=False` gives the floating
-    (no boundary condition) variant used for null-space checks."""
+    (no boundary condition) variant used for null-space checks.  `distort` > 0 moves
+    every interior node by U[-distort, distort] * h per coordinate (default_rng(seed)),
+    so elements become general trilinear hexahedra while the boundary, and hence the
+    union of the elements, stays the unit cube (keep distort below about 0.25)."""
     if n < 1:
         raise ValueError("n must be >= 1")
     m = n + 1
@@ -72,6 +75,10 @@ def make_mesh(n: int, clamp: bool = True) -> Q1Mesh:
     j = (idx // m) % m
     k = idx // (m * m)
     coords = np.stack([i, j, k], axis=1).astype(np.float64) / n
+    if distort > 0:
+        interior = (i > 0) & (i < n) & (j > 0) & (j < n) & (k > 0) & (k < n)
+        d = np.random.default_rng(seed).uniform(-distort, distort, (m ** 3, 3)) / n
+        coords[interior] += d[interior]
     dirichlet = (i == 0) if clamp else np.zeros(m ** 3, dtype=bool)
     e = np.arange(n ** 3, dtype=np.int64)
     ex = e % n
