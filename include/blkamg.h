@@ -74,6 +74,7 @@ typedef struct bsr_s* bsr_t;
 typedef struct coo_plan_s* coo_plan_t;
 typedef struct amg_s* amg_t;
 typedef struct sa_result_s* sa_result_t;
+typedef struct fe_plan_s* fe_plan_t;
 
 /* Thread-local text of the last error ("" if none).  Never NULL. */
 const char* blkamg_last_error(void);
@@ -204,6 +205,50 @@ int coo_plan_map(coo_plan_t plan, const int32_t** d_perm, const int32_t** d_seg,
  * A must be the matrix created with the plan (or have its exact pattern).  Async. */
 int coo_assemble_blocked(coo_plan_t plan, const void* d_vals, int val_dtype, int mode,
                          bsr_t A, void* stream);
+
+/* ==========================================================================
+ * Finite-element assembly of trilinear hexahedral elasticity on the device
+ * (paper §5: finite-element assembly is the blocked COO primitive's immediate use
+ * beyond the Galerkin product; this pairs it with element-by-element assembly).
+ * Element e has 8 nodes d_elem_nodes[8e .. 8e+7] (int32 rows of d_coords, local
+ * order (0,0,0), (1,0,0), (0,1,0), (1,1,0), (0,0,1), (1,0,1), (0,1,1), (1,1,1) of
+ * the reference cube, x fastest) and Lame parameters d_lam[e], d_mu[e]; d_coords is
+ * double [n_nodes][3].  The element stiffness of  int lambda div u div v +
+ * 2 mu eps(u):eps(v)  uses the isoparametric map and 2x2x2 Gauss-Legendre points;
+ * block K_ab (3x3, row-major) couples local nodes a (rows) and b (columns).  Node
+ * indices are not checked on the device: they must index d_coords.
+ * ========================================================================== */
+#define BLKAMG_FE_ATOMIC 0   /* element-by-element, FP64 atomic adds */
+#define BLKAMG_FE_COLORED 1  /* element-by-element in colour passes, fixed order */
+
+/* Element blocks as a blocked COO value stream: d_out double [n_elem*64 + n_identity]
+ * [3][3], element-major with block 64e + 8a + b = K_ab of element e, followed by
+ * n_identity identity blocks (e.g. the Dirichlet diagonal of a clamped mesh).  Feed it
+ * to coo_assemble_blocked with the matching coordinates.  Async, no allocation. */
+int fe_q1_stream(int64_t n_elem, const int32_t* d_elem_nodes, const double* d_coords,
+                 const double* d_lam, const double* d_mu, int64_t n_identity,
+                 double* d_out, void* stream);
+/* Plan for element-by-element assembly into A (square, 3x3 F64 blocks, one block row
+ * per node): the block of A that receives each (e, a, b) (none when either node is
+ * flagged in h_dirichlet, which may be NULL), the diagonal blocks of the flagged
+ * nodes, and a greedy colouring in which elements of one colour share no node (at
+ * most 64 colours; 8 on structured hexahedral meshes).  h_elem_nodes is the host copy
+ * of the element list later passed on the device.  EINVAL if the pattern of A lacks a
+ * needed block or a node is out of range.  Sync; allocates (plan owned by the caller,
+ * fe_ebe_plan_destroy). */
+int fe_ebe_plan_create(bsr_t A, int64_t n_elem, const int32_t* h_elem_nodes,
+                       const uint8_t* h_dirichlet, fe_plan_t* out);
+/* Number of colours and the plan's device bytes (slots, Dirichlet slots, order). */
+int fe_ebe_plan_info(fe_plan_t P, int32_t* n_colors, int64_t* slot_bytes);
+int fe_ebe_plan_destroy(fe_plan_t P);
+/* A's values := sum of the element blocks (identity on the flagged diagonal blocks,
+ * couplings of flagged nodes dropped), computed and added element by element without
+ * a value stream.  mode BLKAMG_FE_ATOMIC: one launch, FP64 atomic adds (the summation
+ * order varies from run to run); BLKAMG_FE_COLORED: one launch per colour with plain
+ * read-modify-writes (deterministic).  Bumps A's value stamp.  Async, no allocation. */
+int fe_q1_assemble_ebe(fe_plan_t P, bsr_t A, const int32_t* d_elem_nodes,
+                       const double* d_coords, const double* d_lam, const double* d_mu,
+                       int mode, void* stream);
 
 /* ==========================================================================
  * Smoothed-aggregation hierarchy and solve (paper §2.1, §2.2, §3.1, §4.1)

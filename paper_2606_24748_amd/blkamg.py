@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("BLKAMG_LIB") or os.path.join(_HERE, "libblkamg.so")
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EBREAKDOWN, ENOTSPD = 0, 1, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 INSERT, ADD = 0, 1
+FE_ATOMIC, FE_COLORED = 0, 1
 EIG_LANCZOS, EIG_MLP = 0, 1
 MLP_PARAMS, MLP_MODEL = 5122, 5150
 
@@ -77,6 +78,11 @@ _SIG = {
     "coo_plan_destroy": (C.c_int, [_p]),
     "coo_plan_map": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_i64), C.POINTER(_i64)]),
     "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
+    "fe_q1_stream": (C.c_int, [_i64, _p, _p, _p, _p, _i64, _p, _p]),
+    "fe_ebe_plan_create": (C.c_int, [_p, _i64, _p, _p, C.POINTER(_p)]),
+    "fe_ebe_plan_info": (C.c_int, [_p, _pi32, C.POINTER(_i64)]),
+    "fe_ebe_plan_destroy": (C.c_int, [_p]),
+    "fe_q1_assemble_ebe": (C.c_int, [_p, _p, _p, _p, _p, _p, C.c_int, _p]),
     "blkamg_opts_default": (None, [C.POINTER(Opts)]),
     "sa_aggregate": (C.c_int, [_i32, _p, _p, _p, _p, _pi32]),
     "sa_setup_host": (C.c_int, [_i32, _p, _p, _p, _p, C.POINTER(Opts), C.POINTER(_p)]),
@@ -295,6 +301,71 @@ def coo_plan_create(nbr, nbc, bs_r, bs_c, i: np.ndarray, j: np.ndarray, val_dtyp
 def coo_assemble_blocked(plan: CooPlan, vals, mode, A: Bsr, stream=None):
     _check(_lib.coo_assemble_blocked(plan.h, _ptr(vals), dtype_code(vals), mode, A.h, _stream(stream)),
            "coo_assemble_blocked")
+
+
+def _fe_inputs(elem_nodes, coords, lam, mu, check_nodes=True):
+    """Check the element inputs: contiguous device tensors, int32 [n_elem, 8] nodes,
+    float64 [n_nodes, 3] coordinates, float64 [n_elem] Lame parameters; with
+    check_nodes, also that every node indexes a row of coords (one reduction and a
+    sync: callers that time the kernels check once and then pass False)."""
+    import torch
+    want = ((elem_nodes, torch.int32), (coords, torch.float64), (lam, torch.float64), (mu, torch.float64))
+    for t, dt in want:
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous device tensor of {dt}")
+    n_elem = elem_nodes.shape[0]
+    if elem_nodes.shape != (n_elem, 8) or coords.dim() != 2 or coords.shape[1] != 3 or \
+            lam.numel() != n_elem or mu.numel() != n_elem:
+        raise ValueError("element input shapes do not match")
+    if check_nodes and n_elem > 0:
+        lo, hi = int(elem_nodes.min()), int(elem_nodes.max())
+        if lo < 0 or hi >= coords.shape[0]:
+            raise ValueError("an element node does not index a row of coords")
+    return n_elem
+
+
+def fe_q1_stream(elem_nodes, coords, lam, mu, out, n_identity=0, stream=None, check_nodes=True):
+    """Element stiffness blocks of trilinear hexahedra into the blocked COO value stream
+    `out` (device F64, [n_elem * 64 + n_identity, 3, 3]); all inputs device tensors."""
+    import torch
+    n_elem = _fe_inputs(elem_nodes, coords, lam, mu, check_nodes)
+    if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != (n_elem * 64 + n_identity) * 9:
+        raise ValueError("out must be a contiguous float64 tensor of (n_elem * 64 + n_identity) * 9 values")
+    _check(_lib.fe_q1_stream(n_elem, _ptr(elem_nodes), _ptr(coords), _ptr(lam), _ptr(mu), n_identity, _ptr(out),
+                             _stream(stream)), "fe_q1_stream")
+
+
+class FePlan:
+    def __init__(self, h, A):
+        self.h = h
+        self._A = A
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fe_ebe_plan_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        nc, nb = _i32(), _i64()
+        _check(_lib.fe_ebe_plan_info(self.h, C.byref(nc), C.byref(nb)), "fe_ebe_plan_info")
+        return {"n_colors": nc.value, "bytes": nb.value}
+
+
+def fe_ebe_plan_create(A: Bsr, elem_nodes: np.ndarray, dirichlet=None) -> FePlan:
+    en = np.ascontiguousarray(elem_nodes, dtype=np.int32)
+    dd = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    h = _p()
+    _check(_lib.fe_ebe_plan_create(A.h, en.shape[0], en.ctypes.data_as(_p),
+                                   dd.ctypes.data_as(_p) if dd is not None else None, C.byref(h)),
+           "fe_ebe_plan_create")
+    return FePlan(h, A)
+
+
+def fe_q1_assemble_ebe(P: FePlan, A: Bsr, elem_nodes, coords, lam, mu, mode=FE_COLORED, stream=None,
+                       check_nodes=True):
+    _fe_inputs(elem_nodes, coords, lam, mu, check_nodes)
+    _check(_lib.fe_q1_assemble_ebe(P.h, A.h, _ptr(elem_nodes), _ptr(coords), _ptr(lam), _ptr(mu), mode,
+                                   _stream(stream)), "fe_q1_assemble_ebe")
 
 
 def blkamg_opts_default() -> Opts:

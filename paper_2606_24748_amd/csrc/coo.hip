@@ -72,7 +72,9 @@ void launch_sum(const coo_plan_s* p, const T* vals, T* out, int add, hipStream_t
   const int be = p->br * p->bc;
   const int64_t total = p->nnzb * be;
   const int64_t grid = (total + 255) / 256;
-  if (be == 9 && grid < INT32_MAX) {
+  if (be == 1 && grid < INT32_MAX) {
+    coo_sum_kernel<T, 1><<<static_cast<int>(grid), 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
+  } else if (be == 9 && grid < INT32_MAX) {
     coo_sum_kernel<T, 9><<<static_cast<int>(grid), 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
   } else if (be == 18 && grid < INT32_MAX) {
     coo_sum_kernel<T, 18><<<static_cast<int>(grid), 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
