@@ -90,7 +90,11 @@ def parse_args(argv=None):
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-eigenbound section")
     ap.add_argument("--no-q2", action="store_true", help="skip the triquadratic (Q2) section")
     ap.add_argument("--q2-n", type=int, default=64, help="elements per edge of the Q2 problem")
-    ap.add_argument("--only-section", choices=("learned", "batch", "q2"), default=None,
+    ap.add_argument("--no-fe", action="store_true", help="skip the finite-element assembly section")
+    ap.add_argument("--fe-n", type=int, default=128, help="elements per edge of the FE assembly problem")
+    ap.add_argument("--fe-scalar-n", type=int, default=64,
+                    help="elements per edge of the blocked vs scalar COO comparison")
+    ap.add_argument("--only-section", choices=("learned", "batch", "q2", "fe"), default=None,
                     help="run only that section and print its result (profiling runs)")
     ap.add_argument("--learned-n", type=int, default=96, help="edge of the learned-eigenbound deployment problem")
     ap.add_argument("--model", default=None, help="eigenbound model JSON (default: the packaged one)")
@@ -299,6 +303,104 @@ def run_q2(args, B, RL, torch, dev, stream):
     return res
 
 
+def _event_ms(torch, stream, fn, reps):
+    """Average duration of fn() over reps calls, HIP events on the launch stream."""
+    for _ in range(2):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_fe(args, B, torch, dev, stream):
+    """Standalone finite-element assembly (the blocked COO primitive's use beyond the
+    Galerkin product, paper §5).  Q1 elasticity on a distorted fe_n^3 mesh (interior nodes
+    moved by up to 0.2 h, seed 31; materials seed 11): the device element kernel writing
+    the blocked COO value stream, blocked COO assembly of that stream, and
+    element-by-element assembly without a stream (FP64 atomics; colour passes).  Then, at
+    fe_scalar_n^3, the same stream assembled as blocked COO and as scalar COO (1x1 blocks
+    at coordinates 3i+c, 3j+d): plan size and assembly time."""
+    import numpy as np
+
+    import synth
+
+    reps = max(args.steps, 3)
+    res = {}
+    for n, scalar in ((args.fe_n, False), (args.fe_scalar_n, True)):
+        t0 = time.perf_counter()
+        m = synth.make_mesh(n, distort=0.2, seed=31)
+        lam, mu = synth.lame(*synth.materials(m.n_elem, 11))
+        en = torch.as_tensor(m.elem_nodes.astype(np.int32), device=dev)
+        X = torch.as_tensor(m.coords, device=dev)
+        lam_t, mu_t = torch.as_tensor(lam, device=dev), torch.as_tensor(mu, device=dev)
+        i, j = synth.coo_indices(m)
+        vals = torch.empty((m.n_elem * 64 + m.n_dirichlet, 3, 3), dtype=torch.float64, device=dev)
+        plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+        perm, seg = plan.index_map()
+        n_valid, nnzb = perm.numel(), seg.numel() - 1
+        del perm, seg
+        B.fe_q1_stream(en, X, lam_t, mu_t, vals, m.n_dirichlet)  # checks the node range once
+        log(f"[fe] n={n}: {m.n_elem} elements, nnzb {nnzb} ({time.perf_counter() - t0:.1f}s)")
+        r = {"n": n, "elements": m.n_elem, "stream_blocks": int(vals.shape[0]), "valid_blocks": n_valid,
+             "nnzb": nnzb, "coo_plan_bytes": 4 * (n_valid + nnzb + 1)}
+        r["element_kernel_ms"] = _event_ms(torch, stream, lambda: B.fe_q1_stream(
+            en, X, lam_t, mu_t, vals, m.n_dirichlet, check_nodes=False), reps)
+        r["element_kernel_bytes"] = vals.numel() * 8 + m.n_elem * (32 + 16) + m.n_nodes * 24
+        r["coo_assemble_ms"] = _event_ms(torch, stream, lambda: B.coo_assemble_blocked(plan, vals, B.INSERT, HA),
+                                         reps)
+        r["coo_assemble_bytes"] = n_valid * (72 + 4) + (nnzb + 1) * 4 + nnzb * 72
+        for k in ("element_kernel", "coo_assemble"):
+            r[k + "_GBs"] = r[k + "_bytes"] / (r[k + "_ms"] * 1e-3) / 1e9
+        if not scalar:
+            ref = HA.arrays()[2].clone()
+            P = B.fe_ebe_plan_create(HA, m.elem_nodes, m.dirichlet)
+            r.update({("ebe_" + k): v for k, v in P.info().items()})
+            for name, mode in (("atomic", B.FE_ATOMIC), ("colored", B.FE_COLORED)):
+                r[f"ebe_{name}_ms"] = _event_ms(torch, stream, lambda: B.fe_q1_assemble_ebe(
+                    P, HA, en, X, lam_t, mu_t, mode, check_nodes=False), reps)
+                got = HA.arrays()[2]
+                r[f"ebe_{name}_max_rel_diff"] = float((got - ref).abs().max() / ref.abs().max())
+                del got
+            r["stream_plus_coo_ms"] = r["element_kernel_ms"] + r["coo_assemble_ms"]
+            log(f"[fe] element kernel {r['element_kernel_ms']:.2f} ms ({r['element_kernel_GBs']:.0f} GB/s), "
+                f"blocked COO {r['coo_assemble_ms']:.2f} ms ({r['coo_assemble_GBs']:.0f} GB/s); element by "
+                f"element: atomic {r['ebe_atomic_ms']:.2f} ms, {r['ebe_n_colors']} colours "
+                f"{r['ebe_colored_ms']:.2f} ms")
+            del P, ref
+            res["assembly"] = r
+        else:
+            c = np.arange(3, dtype=np.int32)
+            isc = np.where(i[:, None, None] >= 0, 3 * i[:, None, None] + c[None, :, None], -1)
+            isc = np.broadcast_to(isc, (len(i), 3, 3)).reshape(-1).astype(np.int32)
+            jsc = np.where(j[:, None, None] >= 0, 3 * j[:, None, None] + c[None, None, :], -1)
+            jsc = np.broadcast_to(jsc, (len(j), 3, 3)).reshape(-1).astype(np.int32)
+            t0 = time.perf_counter()
+            plan1, H1 = B.coo_plan_create(m.n_dof, m.n_dof, 1, 1, isc, jsc)
+            r["scalar_plan_create_s"] = time.perf_counter() - t0
+            del isc, jsc
+            perm, seg = plan1.index_map()
+            nv1, nnz1 = perm.numel(), seg.numel() - 1
+            del perm, seg
+            r.update({"scalar_valid_entries": nv1, "scalar_nnz": nnz1, "scalar_coo_plan_bytes": 4 * (nv1 + nnz1 + 1)})
+            r["scalar_coo_assemble_ms"] = _event_ms(torch, stream, lambda: B.coo_assemble_blocked(
+                plan1, vals, B.INSERT, H1), reps)
+            r["plan_bytes_ratio"] = r["scalar_coo_plan_bytes"] / r["coo_plan_bytes"]
+            r["assemble_time_ratio"] = r["scalar_coo_assemble_ms"] / r["coo_assemble_ms"]
+            log(f"[fe] n={n} blocked COO {r['coo_assemble_ms']:.3f} ms, plan {r['coo_plan_bytes'] / 1e6:.0f} MB; "
+                f"scalar COO {r['scalar_coo_assemble_ms']:.3f} ms, plan {r['scalar_coo_plan_bytes'] / 1e6:.0f} MB")
+            del plan1, H1
+            res["blocked_vs_scalar"] = r
+        del plan, HA, vals, en, X, lam_t, mu_t
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_learned(args, B, torch, dev, stream):
     """Deployment of the learned eigenbound on Q1 elasticity at learned_n^3 elements
     (material seed 21, redraw 1021, right-hand side seed 22): FP32 hierarchy with
@@ -487,6 +589,8 @@ def main(argv=None):
         stream = torch.cuda.current_stream()
         if args.only_section == "q2":
             result = run_q2(args, B, RL, torch, dev, stream)
+        elif args.only_section == "fe":
+            result = run_fe(args, B, torch, dev, stream)
         else:
             run = run_learned if args.only_section == "learned" else run_batch
             result = run(args, B, torch, dev, stream)
@@ -523,8 +627,12 @@ def main(argv=None):
     batch = None
     learned = None
     q2 = None
+    fe = None
     del plan, HA, vals
     torch.cuda.empty_cache()
+    if not args.no_fe:
+        fe = run_fe(args, B, torch, dev, stream)
+        torch.cuda.empty_cache()
     if not args.no_q2:
         q2 = run_q2(args, B, RL, torch, dev, stream)
         torch.cuda.empty_cache()
@@ -570,6 +678,7 @@ def main(argv=None):
         "batch": batch,
         "learned": learned,
         "q2": q2,
+        "fe": fe,
         "coo_plan_s": t_plan,
     }
     if "fp64" in results and head != "fp64":

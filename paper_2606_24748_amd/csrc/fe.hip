@@ -33,6 +33,13 @@ namespace {
 
 constexpr int kFeWaves = 4;  // elements per 256-thread workgroup
 constexpr int kFeGeo = 10;   // per Gauss point: J^-1 (row-major) and det(J) / 8
+#ifndef BLK_FE_QUNROLL
+#define BLK_FE_QUNROLL 2
+#endif
+// Gauss points per loop trip.  Two keep the kernel at about 90 VGPRs (5 waves per SIMD
+// to cover the latency of the dependent node and coordinate loads) instead of ~130
+// (3 waves) fully unrolled; measured at 128^3: 3.48 ms (2 per trip), 3.56 (1), 3.70 (8).
+constexpr int kFeQUnroll = BLK_FE_QUNROLL;
 
 enum FeMode { kStream = 0, kAtomic = 1, kPlain = 2 };
 
@@ -58,6 +65,8 @@ __global__ __launch_bounds__(256) void fe_q1_kernel(int64_t count, const int32_t
                                                     const double* __restrict__ mu, const int32_t* __restrict__ slot,
                                                     double* __restrict__ out) {
   __shared__ double geo[kFeWaves][8][kFeGeo];
+  // stream mode: the wave's 64 blocks, written out as one contiguous 4.6 KB run
+  __shared__ __align__(16) double kout[kMode == kStream ? kFeWaves : 1][kMode == kStream ? 64 * 9 : 2];
   const int w = static_cast<int>(threadIdx.x) / 64, lane = static_cast<int>(threadIdx.x) % 64;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * kFeWaves + w;
   const bool live = idx < count;
@@ -91,10 +100,13 @@ __global__ __launch_bounds__(256) void fe_q1_kernel(int64_t count, const int32_t
     G[9] = det * 0.125;
   }
   __syncthreads();
-  if (!live) return;
+  // waves past the end compute on unset geometry and store nothing; they stay to the
+  // end so that every wave reaches the second barrier of the stream mode
   const int a = lane >> 3, b = lane & 7;
-  const double l = lam[e], m = mu[e];
-  double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // lambda and mu are constant on the element, so with S = sum_q w det(J) g_a g_b^T
+  // the block is  lambda S + mu (S^T + tr(S) I): one outer product per point
+  double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll kFeQUnroll
   for (int q = 0; q < 8; ++q) {
     const double* G = geo[w][q];
     const double x = gauss_coord(q & 1), y = gauss_coord((q >> 1) & 1), z = gauss_coord((q >> 2) & 1);
@@ -107,21 +119,31 @@ __global__ __launch_bounds__(256) void fe_q1_kernel(int64_t count, const int32_t
       gb[c] = rb[0] * G[c] + rb[1] * G[3 + c] + rb[2] * G[6 + c];
     }
     const double wd = G[9];
-    const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+      const double wa = wd * ga[c];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double v = l * ga[c] * gb[d] + m * ga[d] * gb[c];
-        if (c == d) v += m * dot;
-        K[c * 3 + d] += wd * v;
-      }
+      for (int d = 0; d < 3; ++d) S[c * 3 + d] += wa * gb[d];
+    }
   }
-  if constexpr (kMode == kStream) {
-    double* o = out + (e * 64 + lane) * 9;
+  const double l = lam[e], m = mu[e];
+  const double mt = m * (S[0] + S[4] + S[8]);
+  double K[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) o[t] = K[t];
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) K[c * 3 + d] = l * S[c * 3 + d] + m * S[d * 3 + c] + (c == d ? mt : 0.0);
+  if constexpr (kMode == kStream) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) kout[w][lane * 9 + t] = K[t];
+    __syncthreads();
+    if (live) {
+      const double2* src = reinterpret_cast<const double2*>(kout[w]);
+      double2* dst = reinterpret_cast<double2*>(out + e * 64 * 9);
+      for (int k = lane; k < 64 * 9 / 2; k += 64) dst[k] = src[k];
+    }
   } else {
+    if (!live) return;
     const int s = slot[e * 64 + lane];
     if (s >= 0) {
       double* o = out + static_cast<int64_t>(s) * 9;
