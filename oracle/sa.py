@@ -7,9 +7,10 @@ from __future__ import annotations
 import numpy as np
 
 from . import sparse as S
-from .mix import start_vector
+from .mix import splitmix64, start_vector
 
 LANCZOS_SEED = 0x5EED
+LUBY_SEED = 0x4D495332
 
 
 def strength_graph(A: S.Bsr, dirichlet: np.ndarray, eps: float = 0.0):
@@ -83,6 +84,76 @@ def aggregate(nbrs, dirichlet: np.ndarray):
             agg[i] = n_agg
             n_agg += 1
     return np.array(agg, dtype=np.int64), n_agg
+
+
+def luby_keys(n: int, seed: int) -> list:
+    """Priority of vertex i in the parallel aggregation: the high 32 bits of
+    splitmix64(seed XOR i) above i + 1 in the low 32 bits, so keys are distinct and
+    positive (0 is free to mean "none")."""
+    return [((splitmix64(seed ^ i) >> 32) << 32) | (i + 1) for i in range(n)]
+
+
+def _within2(nbrs, i):
+    """Vertices at graph distance 1 or 2 from i (i excluded)."""
+    out = set(nbrs[i])
+    for j in nbrs[i]:
+        out.update(nbrs[j])
+    out.discard(i)
+    return out
+
+
+def aggregate_luby(nbrs, dirichlet: np.ndarray, seed: int = LUBY_SEED):
+    """Parallel disjoint covering (paper §6, the device MIS coarsener: Luby rounds with
+    deterministic hash priorities), in the notation of `aggregate`.
+
+    Distance-2 MIS by rounds: every undecided vertex whose key exceeds the keys of all
+    undecided vertices within distance 2 becomes a root; then every undecided vertex
+    within distance 2 of a new root is decided (not a root).  Repeat until no vertex is
+    undecided.  Roots are numbered in increasing vertex order.  Phase 1: each neighbour
+    of a root joins that root's aggregate (roots are at least 3 apart, so the root is
+    unique).  Phase 2: a remaining vertex joins the phase-1 aggregate that holds the most
+    of its neighbours, ties going to the smallest aggregate id (as in `aggregate`).
+    Dirichlet vertices stay unaggregated (-1).  Returns (agg[n] int64, n_agg, rounds)."""
+    n = len(nbrs)
+    key = luby_keys(n, seed)
+    UND, ROOT, OUT = 0, 1, 2
+    state = [OUT if dirichlet[i] else UND for i in range(n)]
+    rounds = 0
+    while any(s == UND for s in state):
+        rounds += 1
+        new = [i for i in range(n) if state[i] == UND and
+               all(not (state[j] == UND and key[j] > key[i]) for j in _within2(nbrs, i))]
+        for i in new:
+            state[i] = ROOT
+        for i in new:
+            for j in _within2(nbrs, i):
+                if state[j] == UND:
+                    state[j] = OUT
+    agg = [-1] * n
+    n_agg = 0
+    for i in range(n):
+        if state[i] == ROOT:
+            agg[i] = n_agg
+            n_agg += 1
+    phase1 = list(agg)
+    for i in range(n):
+        if dirichlet[i] or phase1[i] >= 0:
+            continue
+        roots = [phase1[j] for j in nbrs[i] if state[j] == ROOT]
+        if roots:
+            agg[i] = roots[0]
+    phase1 = list(agg)
+    for i in range(n):
+        if dirichlet[i] or phase1[i] >= 0:
+            continue
+        count = {}
+        for j in nbrs[i]:
+            g = phase1[j]
+            if g >= 0:
+                count[g] = count.get(g, 0) + 1
+        best = max(count.values())
+        agg[i] = min(g for g, c in count.items() if c == best)
+    return np.array(agg, dtype=np.int64), n_agg, rounds
 
 
 def rigid_body_modes(coords: np.ndarray) -> np.ndarray:

@@ -23,6 +23,8 @@ class Options:
     lanczos_steps: int = 10
     lanczos_seed: int = sa.LANCZOS_SEED
     omega_scale: float = 4.0 / 3.0
+    agg_mode: str = "greedy"        # "greedy" (natural order) or "luby" (parallel rounds)
+    agg_seed: int = sa.LUBY_SEED
 
 
 @dataclass
@@ -150,7 +152,10 @@ def setup(A0: S.Bsr, coords: np.ndarray, dirichlet: np.ndarray, opts: Options | 
     lev = 0
     while A.nbr * A.br > o.coarse_eq_limit and lev < o.max_levels - 1:
         nbrs = sa.strength_graph(A, dmask, o.strength_eps)
-        agg, n_agg = sa.aggregate(nbrs, dmask)
+        if o.agg_mode == "luby":
+            agg, n_agg, _ = sa.aggregate_luby(nbrs, dmask, o.agg_seed)
+        else:
+            agg, n_agg = sa.aggregate(nbrs, dmask)
         if n_agg == 0:
             break
         Pt, Bc = sa.tentative_prolongator(agg, n_agg, B)
