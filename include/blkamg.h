@@ -218,6 +218,8 @@ int coo_assemble_blocked(coo_plan_t plan, const void* d_vals, int val_dtype, int
  * block K_ab (3x3, row-major) couples local nodes a (rows) and b (columns).  Node
  * indices are not checked on the device: they must index d_coords.
  * ========================================================================== */
+#define BLKAMG_AGG_GREEDY 0
+#define BLKAMG_AGG_LUBY 1
 #define BLKAMG_FE_ATOMIC 0   /* element-by-element, FP64 atomic adds */
 #define BLKAMG_FE_COLORED 1  /* element-by-element in colour passes, fixed order */
 
@@ -274,6 +276,10 @@ typedef struct {
   int32_t eig_mode;         /* BLKAMG_EIG_LANCZOS (default) or BLKAMG_EIG_MLP: refreshes
                                take lambda_hat from the model set by amg_set_eig_model
                                (the cold setup always uses Lanczos) */
+  int32_t agg_mode;         /* BLKAMG_AGG_GREEDY (default): host aggregation in natural
+                               order; BLKAMG_AGG_LUBY: sa_aggregate_device with agg_seed
+                               on every level (one instance, strength_eps = 0) */
+  uint64_t agg_seed;        /* priority seed of BLKAMG_AGG_LUBY, default 0x4D495332 */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -290,6 +296,21 @@ void blkamg_opts_default(blkamg_opts* o);
 int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
                  const uint8_t* h_dirichlet, int32_t* h_agg, int32_t* n_agg);
 
+/* Distance-2 aggregation on the device by Luby rounds (paper §6: the device MIS
+ * coarsener with deterministic hash priorities).  The graph is the block pattern of
+ * A (square, any block size and dtype; values unused) without the diagonal and
+ * without the vertices flagged in d_dirichlet (device uint8[nbr], may be NULL).
+ * Vertex i has priority ((splitmix64(seed ^ i) >> 32) << 32) | (i + 1).  Each round,
+ * an undecided vertex whose priority is the largest among undecided vertices within
+ * distance 2 becomes a root, then undecided vertices within distance 2 of a new root
+ * are decided; rounds repeat until none is undecided.  Roots are numbered in vertex
+ * order; a root's neighbours join it; the remaining vertices join the neighbouring
+ * aggregate that holds most of their neighbours (ties: smallest id).  d_agg: device
+ * int32[nbr] output (-1 for flagged vertices); *n_agg aggregates; *n_rounds (may be
+ * NULL) rounds taken.  The pattern's rows must be symmetric (an undirected graph).
+ * Sync (one 4-byte read per round); allocates scratch. */
+int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg,
+                        int32_t* n_agg, int32_t* n_rounds, void* stream);
 /* One smoothed-aggregation level on the host from the fine block pattern (paper §2.2,
  * §3.2): the greedy aggregation of sa_aggregate, the tentative prolongator P~ of the
  * six rigid-body modes built from h_coords ([n_nodes][3], bs = 3: per aggregate a thin

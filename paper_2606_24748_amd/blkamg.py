@@ -19,6 +19,8 @@ OK, ENOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EBREAKDOWN, ENOTSPD = 0, 1, -1, -2, -
 F64, F32, BF16 = 0, 1, 2
 INSERT, ADD = 0, 1
 FE_ATOMIC, FE_COLORED = 0, 1
+AGG_GREEDY, AGG_LUBY = 0, 1
+LUBY_SEED = 0x4D495332
 EIG_LANCZOS, EIG_MLP = 0, 1
 MLP_PARAMS, MLP_MODEL = 5122, 5150
 
@@ -56,6 +58,8 @@ class Opts(C.Structure):
         ("pcg_graph_iters", C.c_int32),
         ("autotune_nrhs", C.c_int32),
         ("eig_mode", C.c_int32),
+        ("agg_mode", C.c_int32),
+        ("agg_seed", C.c_uint64),
     ]
 
 
@@ -78,6 +82,7 @@ _SIG = {
     "coo_plan_destroy": (C.c_int, [_p]),
     "coo_plan_map": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_i64), C.POINTER(_i64)]),
     "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
+    "sa_aggregate_device": (C.c_int, [_p, _p, C.c_uint64, _p, _pi32, _pi32, _p]),
     "fe_q1_stream": (C.c_int, [_i64, _p, _p, _p, _p, _i64, _p, _p]),
     "fe_ebe_plan_create": (C.c_int, [_p, _i64, _p, _p, C.POINTER(_p)]),
     "fe_ebe_plan_info": (C.c_int, [_p, _pi32, C.POINTER(_i64)]),
@@ -301,6 +306,23 @@ def coo_plan_create(nbr, nbc, bs_r, bs_c, i: np.ndarray, j: np.ndarray, val_dtyp
 def coo_assemble_blocked(plan: CooPlan, vals, mode, A: Bsr, stream=None):
     _check(_lib.coo_assemble_blocked(plan.h, _ptr(vals), dtype_code(vals), mode, A.h, _stream(stream)),
            "coo_assemble_blocked")
+
+
+def sa_aggregate_device(A: Bsr, dirichlet=None, seed=LUBY_SEED, stream=None):
+    """Distance-2 aggregation of A's block graph on the device (Luby rounds).
+    Returns (agg device int32 tensor, n_agg, rounds); dirichlet: host bool/uint8 or None."""
+    import torch
+    n = A.info()["nbr"]
+    agg = torch.empty(n, dtype=torch.int32, device="cuda")
+    d = None
+    if dirichlet is not None:
+        d = torch.as_tensor(np.ascontiguousarray(dirichlet, dtype=np.uint8)).cuda()
+        if d.numel() != n:
+            raise ValueError("dirichlet must have one flag per block row")
+    na, nr = _i32(), _i32()
+    _check(_lib.sa_aggregate_device(A.h, _ptr(d), seed, _ptr(agg), C.byref(na), C.byref(nr), _stream(stream)),
+           "sa_aggregate_device")
+    return agg, na.value, nr.value
 
 
 def _fe_inputs(elem_nodes, coords, lam, mu, check_nodes=True):

@@ -909,6 +909,21 @@ std::vector<int32_t> aggregate_segments(Level& L, const std::vector<uint8_t>& di
   return cnt;
 }
 
+// Aggregation of a one-instance level on the device (Luby rounds); `agg` gets the ids.
+std::vector<int32_t> aggregate_level_device(Level& L, const std::vector<uint8_t>& dir, uint64_t seed,
+                                            std::vector<int32_t>& agg, hipStream_t s) {
+  bsr_s* A = L.A_act.get();
+  BLK_REQUIRE(L.n_act == 1 && A->nbr == A->nbc, BLKAMG_EINVAL, "device aggregation takes one instance");
+  DevBuf<uint8_t> ddir;
+  if (!dir.empty()) upload(ddir, dir);
+  DevBuf<int32_t> dagg(static_cast<size_t>(A->nbr));
+  int32_t n_agg = 0;
+  const int rc = sa_aggregate_device(A, dir.empty() ? nullptr : ddir.p, seed, dagg.p, &n_agg, nullptr, s);
+  if (rc != BLKAMG_OK) fail(rc, std::string("sa_aggregate_device: ") + blkamg_last_error());
+  agg = download(dagg.p, static_cast<size_t>(A->nbr));
+  return {n_agg};
+}
+
 // Block-diagonal structure check of the instances of A0 (host pattern).
 void check_block_diagonal(bsr_s* A, const std::vector<int32_t>& row0) {
   ensure_host_pattern(A);
@@ -948,6 +963,7 @@ void check_opts(const blkamg_opts& o) {
   BLK_REQUIRE(o.autotune_nrhs == 0 || o.autotune_nrhs == 1 || o.autotune_nrhs == 8, BLKAMG_EINVAL,
               "autotune_nrhs must be 0, 1 or 8");
   BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
+  BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || o.agg_mode == BLKAMG_AGG_LUBY, BLKAMG_EINVAL, "bad agg_mode");
 }
 
 // The parts of a hierarchy that do not depend on how its levels were made.
@@ -1003,6 +1019,8 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   BLK_REQUIRE(A0->nbr > 0, BLKAMG_EINVAL, "A0 is empty");
   check_opts(o);
   BLK_REQUIRE(n_inst >= 1 && n_inst <= 65535, BLKAMG_EINVAL, "n_inst must be in 1..65535");
+  BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || (n_inst == 1 && o.strength_eps == 0.0), BLKAMG_EINVAL,
+              "device aggregation takes one instance and the structural graph (strength_eps = 0)");
   std::vector<int32_t> row0(static_cast<size_t>(n_inst) + 1);
   if (h_row0) {
     std::copy(h_row0, h_row0 + n_inst + 1, row0.begin());
@@ -1051,7 +1069,9 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     std::vector<uint8_t> strong;
     if (o.strength_eps > 0) strong = strength_mask(L.A_act.get(), o.strength_eps);
     std::vector<int32_t> agg;
-    const std::vector<int32_t> cnt = aggregate_segments(L, dir, strong, agg);
+    const std::vector<int32_t> cnt = o.agg_mode == BLKAMG_AGG_LUBY
+                                         ? aggregate_level_device(L, dir, o.agg_seed, agg, s)
+                                         : aggregate_segments(L, dir, strong, agg);
     bool empty = false;
     for (int32_t c : cnt) empty = empty || c == 0;
     if (empty) {
@@ -1439,6 +1459,8 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->pcg_graph_iters = 4;
   o->autotune_nrhs = 0;
   o->eig_mode = BLKAMG_EIG_LANCZOS;
+  o->agg_mode = BLKAMG_AGG_GREEDY;
+  o->agg_seed = 0x4D495332ull;
 }
 
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream,
