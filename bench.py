@@ -80,8 +80,8 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per cube edge")
-    ap.add_argument("--variants", default="mixed,mixed-mlp,mixed-bf16,fp64",
-                    help="comma list of mixed, mixed-mlp, mixed-bf16, fp64")
+    ap.add_argument("--variants", default="mixed,mixed-mlp,mixed-bf16,mixed-luby,fp64",
+                    help="comma list of mixed, mixed-mlp, mixed-bf16, mixed-luby, fp64")
     ap.add_argument("--probe-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
@@ -317,6 +317,29 @@ def _event_ms(torch, stream, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def run_aggregation(B, torch, HA, dirichlet):
+    """Fine-level aggregation of the 128^3 operator's block graph: the device Luby rounds
+    (best of 3 calls, each synchronous) against the host greedy pass."""
+    import numpy as np
+
+    t_dev = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        agg, n_agg, rounds = B.sa_aggregate_device(HA, dirichlet)
+        t_dev.append(time.perf_counter() - t0)
+    rp, ci, _ = HA.arrays()
+    rp, ci = rp.cpu().numpy(), ci.cpu().numpy()
+    t0 = time.perf_counter()
+    _, n_host = B.sa_aggregate(rp, ci, np.asarray(dirichlet, dtype=np.uint8))
+    t_host = time.perf_counter() - t0
+    res = {"device_s": min(t_dev), "rounds": rounds, "device_aggregates": n_agg, "host_greedy_s": t_host,
+           "host_aggregates": n_host}
+    log(f"[aggregation] device Luby {1e3 * res['device_s']:.1f} ms ({rounds} rounds, {n_agg} aggregates); "
+        f"host greedy {1e3 * t_host:.0f} ms ({n_host} aggregates)")
+    return res
+
+
 def run_fe(args, B, torch, dev, stream):
     """Standalone finite-element assembly (the blocked COO primitive's use beyond the
     Galerkin product, paper §5).  Q1 elasticity on a distorted fe_n^3 mesh (interior nodes
@@ -487,6 +510,8 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
         o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, B.EIG_MLP
     elif var == "mixed-bf16":
         o.hier_dtype, o.p_dtype = B.F32, B.BF16
+    elif var == "mixed-luby":
+        o.hier_dtype, o.p_dtype, o.agg_mode = B.F32, B.F32, B.AGG_LUBY
     else:
         raise SystemExit(f"unknown variant {var}")
     B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
@@ -624,6 +649,7 @@ def main(argv=None):
         results[var] = run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b)
 
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+    aggregation = run_aggregation(B, torch, HA, mesh.dirichlet)
     batch = None
     learned = None
     q2 = None
@@ -679,6 +705,7 @@ def main(argv=None):
         "learned": learned,
         "q2": q2,
         "fe": fe,
+        "aggregation": aggregation,
         "coo_plan_s": t_plan,
     }
     if "fp64" in results and head != "fp64":

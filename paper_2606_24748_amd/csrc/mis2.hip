@@ -4,7 +4,7 @@
 // The graph is the block pattern of A without the diagonal and without Dirichlet
 // vertices.  Vertex i has the priority key_i = (high 32 bits of splitmix64(seed ^ i))
 // above (i + 1), so keys are distinct and positive.  One round is four passes over
-// the pattern, one thread per vertex:
+// the pattern (a group of lanes per vertex):
 //   1. m1_i = largest key of an undecided vertex in {i} and its neighbours;
 //   2. an undecided i whose key equals the largest m1 over {i} and its neighbours
 //      (the largest undecided key within distance 2) becomes a root;
@@ -48,52 +48,86 @@ __global__ void mis_init_kernel(int32_t n, const uint8_t* __restrict__ dir, uint
   state[i] = free_vertex(dir, i) ? kUndecided : kOut;
 }
 
+// The passes over the graph give each vertex a group of kG lanes that stride over its
+// neighbours (consecutive lanes read consecutive column indices) and combine their
+// findings by shuffles; lane 0 of the group writes the vertex's result.
+constexpr int kG = 32;
+
+__device__ __forceinline__ uint64_t group_max(uint64_t v) {
+#pragma unroll
+  for (int off = kG / 2; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, kG);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+struct GroupRow {
+  int32_t i, lane;
+  bool active;
+};
+
+__device__ __forceinline__ GroupRow group_row(int32_t n) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  GroupRow r;
+  r.i = static_cast<int32_t>(g / kG);
+  r.lane = static_cast<int32_t>(g % kG);
+  r.active = r.i < n;
+  return r;
+}
+
 // pass 1: largest undecided key among {i} and its neighbours
 __global__ void mis_max1_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                 const uint8_t* __restrict__ dir, const uint64_t* __restrict__ key,
                                 const uint8_t* __restrict__ state, uint64_t* __restrict__ m1) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
+  const GroupRow r = group_row(n);
+  const bool use = r.active && free_vertex(dir, r.i);
   uint64_t m = 0;
-  if (free_vertex(dir, i)) {
-    if (state[i] == kUndecided) m = key[i];
-    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+  if (use) {
+    if (r.lane == 0 && state[r.i] == kUndecided) m = key[r.i];
+    for (int32_t t = rp[r.i] + r.lane; t < rp[r.i + 1]; t += kG) {
       const int32_t j = ci[t];
-      if (j != i && free_vertex(dir, j) && state[j] == kUndecided) m = key[j] > m ? key[j] : m;
+      if (j != r.i && free_vertex(dir, j) && state[j] == kUndecided) m = key[j] > m ? key[j] : m;
     }
   }
-  m1[i] = m;
+  m = group_max(m);
+  if (r.active && r.lane == 0) m1[r.i] = m;
 }
 
 // pass 2: an undecided vertex holding the largest undecided key within distance 2 becomes a root
 __global__ void mis_select_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const uint8_t* __restrict__ dir, const uint64_t* __restrict__ key,
                                   const uint64_t* __restrict__ m1, uint8_t* __restrict__ state) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n || state[i] != kUndecided) return;
-  uint64_t m = m1[i];
-  for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
-    const int32_t j = ci[t];
-    if (j != i && free_vertex(dir, j)) m = m1[j] > m ? m1[j] : m;
+  const GroupRow r = group_row(n);
+  const bool use = r.active && state[r.i] == kUndecided;
+  uint64_t m = 0;
+  if (use) {
+    if (r.lane == 0) m = m1[r.i];
+    for (int32_t t = rp[r.i] + r.lane; t < rp[r.i + 1]; t += kG) {
+      const int32_t j = ci[t];
+      if (j != r.i && free_vertex(dir, j)) m = m1[j] > m ? m1[j] : m;
+    }
   }
-  if (m == key[i]) state[i] = kNewRoot;
+  m = group_max(m);
+  if (use && r.lane == 0 && m == key[r.i]) state[r.i] = kNewRoot;
 }
 
 // pass 3: a new root among {i} and its neighbours
 __global__ void mis_near_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                 const uint8_t* __restrict__ dir, const uint8_t* __restrict__ state,
                                 uint8_t* __restrict__ near) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  uint8_t f = 0;
-  if (free_vertex(dir, i)) {
-    f = state[i] == kNewRoot;
-    for (int32_t t = rp[i]; t < rp[i + 1] && !f; ++t) {
+  const GroupRow r = group_row(n);
+  const bool use = r.active && free_vertex(dir, r.i);
+  uint64_t f = 0;
+  if (use) {
+    if (r.lane == 0) f = state[r.i] == kNewRoot;
+    for (int32_t t = rp[r.i] + r.lane; t < rp[r.i + 1]; t += kG) {
       const int32_t j = ci[t];
-      if (j != i && free_vertex(dir, j) && state[j] == kNewRoot) f = 1;
+      if (j != r.i && free_vertex(dir, j) && state[j] == kNewRoot) f = 1;
     }
   }
-  near[i] = f;
+  f = group_max(f);
+  if (r.active && r.lane == 0) near[r.i] = static_cast<uint8_t>(f);
 }
 
 // pass 4: decide the undecided vertices within distance 2 of a new root, promote the
@@ -101,18 +135,22 @@ __global__ void mis_near_kernel(int32_t n, const int32_t* __restrict__ rp, const
 __global__ void mis_decide_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const uint8_t* __restrict__ dir, const uint8_t* __restrict__ near,
                                   uint8_t* __restrict__ state, int32_t* __restrict__ n_undecided) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  const uint8_t s = state[i];
-  if (s == kNewRoot) {
-    state[i] = kRoot;
-  } else if (s == kUndecided) {
-    bool hit = near[i] != 0;
-    for (int32_t t = rp[i]; t < rp[i + 1] && !hit; ++t) {
+  const GroupRow r = group_row(n);
+  const uint8_t s = r.active ? state[r.i] : kOut;
+  uint64_t hit = 0;
+  if (s == kUndecided) {
+    if (r.lane == 0) hit = near[r.i] != 0;
+    for (int32_t t = rp[r.i] + r.lane; t < rp[r.i + 1]; t += kG) {
       const int32_t j = ci[t];
-      if (j != i && free_vertex(dir, j) && near[j]) hit = true;
+      if (j != r.i && free_vertex(dir, j) && near[j]) hit = 1;
     }
-    if (hit) state[i] = kOut;
+  }
+  hit = group_max(hit);
+  if (r.lane != 0) return;
+  if (s == kNewRoot) {
+    state[r.i] = kRoot;
+  } else if (s == kUndecided) {
+    if (hit) state[r.i] = kOut;
     else atomicAdd(n_undecided, 1);
   }
 }
@@ -130,54 +168,64 @@ __global__ void mis_root_flag_kernel(int32_t n, const uint8_t* __restrict__ stat
 __global__ void mis_phase1_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const uint8_t* __restrict__ dir, const uint8_t* __restrict__ state,
                                   const int32_t* __restrict__ root_id, int32_t* __restrict__ agg1) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  int32_t g = -1;
-  if (free_vertex(dir, i)) {
-    if (state[i] == kRoot) {
-      g = root_id[i];
-    } else {
-      g = -2;
-      for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
-        const int32_t j = ci[t];
-        if (j != i && free_vertex(dir, j) && state[j] == kRoot) {
-          g = root_id[j];
-          break;
-        }
-      }
+  const GroupRow r = group_row(n);
+  const bool use = r.active && free_vertex(dir, r.i) && state[r.i] != kRoot;
+  uint64_t g = 0;  // root id + 1 of the (unique) neighbouring root, 0 if none
+  if (use) {
+    for (int32_t t = rp[r.i] + r.lane; t < rp[r.i + 1]; t += kG) {
+      const int32_t j = ci[t];
+      if (j != r.i && free_vertex(dir, j) && state[j] == kRoot) g = static_cast<uint64_t>(root_id[j]) + 1;
     }
   }
-  agg1[i] = g;
+  g = group_max(g);
+  if (!r.active || r.lane != 0) return;
+  if (!free_vertex(dir, r.i)) agg1[r.i] = -1;
+  else if (state[r.i] == kRoot) agg1[r.i] = root_id[r.i];
+  else agg1[r.i] = g ? static_cast<int32_t>(g - 1) : -2;
 }
 
 // phase 2: a waiting vertex joins the phase-1 aggregate holding most of its neighbours
+// (ties: smallest id).  Lane l holds the labels of neighbours l, l + kG, ...; each
+// label's count is taken by broadcasting every neighbour label through the group, and
+// (count, -label) is maximised as one 64-bit key.
+__device__ __forceinline__ int32_t neighbour_label(const int32_t* __restrict__ ci, const uint8_t* __restrict__ dir,
+                                                   const int32_t* __restrict__ agg1, int32_t i, int32_t t,
+                                                   int32_t t1) {
+  if (t >= t1) return -1;
+  const int32_t j = ci[t];
+  return (j != i && free_vertex(dir, j)) ? agg1[j] : -1;
+}
+
 __global__ void mis_phase2_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const uint8_t* __restrict__ dir, const int32_t* __restrict__ agg1,
                                   int32_t* __restrict__ agg) {
-  const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  int32_t g = agg1[i];
-  if (g == -2) {
-    int32_t best = -1, best_c = 0;
-    const int32_t t0 = rp[i], t1 = rp[i + 1];
-    for (int32_t t = t0; t < t1; ++t) {
-      const int32_t j = ci[t];
-      if (j == i || !free_vertex(dir, j)) continue;
-      const int32_t h = agg1[j];
-      if (h < 0) continue;
-      int32_t c = 0;
-      for (int32_t u = t0; u < t1; ++u) {
-        const int32_t k = ci[u];
-        if (k != i && free_vertex(dir, k) && agg1[k] == h) ++c;
+  const GroupRow r = group_row(n);
+  const int32_t g1 = r.active ? agg1[r.i] : -1;
+  uint64_t best = 0;
+  if (g1 == -2) {  // the same for every lane of the group
+    const int32_t t0 = rp[r.i], t1 = rp[r.i + 1];
+    for (int32_t c = t0; c < t1; c += kG) {
+      const int32_t h = neighbour_label(ci, dir, agg1, r.i, c + r.lane, t1);
+      uint32_t cnt = 0;
+      for (int32_t c2 = t0; c2 < t1; c2 += kG) {
+        const int32_t h2 = neighbour_label(ci, dir, agg1, r.i, c2 + r.lane, t1);
+        for (int src = 0; src < kG; ++src) {
+          // every lane takes part in the shuffle (a lane that skipped it would not
+          // provide its label to the others)
+          const int32_t o = __shfl(h2, src, kG);
+          cnt += (h >= 0 && o == h) ? 1u : 0u;
+        }
       }
-      if (c > best_c || (c == best_c && h < best)) {
-        best = h;
-        best_c = c;
+      if (h >= 0) {
+        const uint64_t k = (static_cast<uint64_t>(cnt) << 32) | (0xFFFFFFFFull - static_cast<uint32_t>(h));
+        best = k > best ? k : best;
       }
     }
-    g = best;  // every waiting vertex neighbours a phase-1 vertex (maximality)
   }
-  agg[i] = g;
+  best = group_max(best);
+  if (!r.active || r.lane != 0) return;
+  if (g1 != -2) agg[r.i] = g1;
+  else agg[r.i] = best ? static_cast<int32_t>(0xFFFFFFFFull - (best & 0xFFFFFFFFull)) : -1;
 }
 
 }  // namespace
@@ -198,38 +246,55 @@ int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int3
   if (n_rounds) *n_rounds = 0;
   if (n == 0) return BLKAMG_OK;
   hipStream_t s = as_stream(stream);
-  DevBuf<uint64_t> key(static_cast<size_t>(n)), m1(static_cast<size_t>(n));
-  DevBuf<uint8_t> state(static_cast<size_t>(n)), near(static_cast<size_t>(n));
-  DevBuf<int32_t> flag(static_cast<size_t>(n)), root_id(static_cast<size_t>(n)), agg1(static_cast<size_t>(n));
-  DevBuf<int32_t> counter(1);
+  // one scratch allocation, carved into the arrays below (256-byte aligned pieces)
+  const size_t nn = static_cast<size_t>(n);
+  size_t scan_bytes = 0;
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<int32_t*>(nullptr),
+                                             static_cast<int32_t*>(nullptr), n, s));
+  auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  const size_t sizes[] = {nn * 8, nn * 8, nn, nn, nn * 4, nn * 4, nn * 4, 4, std::max<size_t>(scan_bytes, 1)};
+  size_t total = 0;
+  for (size_t b : sizes) total += up(b);
+  DevBuf<char> scratch(total);
+  char* cur = scratch.p;
+  auto take = [&](size_t b) { char* p = cur; cur += up(b); return p; };
+  auto* key = reinterpret_cast<uint64_t*>(take(sizes[0]));
+  auto* m1 = reinterpret_cast<uint64_t*>(take(sizes[1]));
+  auto* state = reinterpret_cast<uint8_t*>(take(sizes[2]));
+  auto* near = reinterpret_cast<uint8_t*>(take(sizes[3]));
+  auto* flag = reinterpret_cast<int32_t*>(take(sizes[4]));
+  auto* root_id = reinterpret_cast<int32_t*>(take(sizes[5]));
+  auto* agg1 = reinterpret_cast<int32_t*>(take(sizes[6]));
+  auto* counter = reinterpret_cast<int32_t*>(take(sizes[7]));
+  void* scan_tmp = take(sizes[8]);
   const int grid = (n + 255) / 256;
-  mis_init_kernel<<<grid, 256, 0, s>>>(n, d_dirichlet, seed, key.p, state.p);
+  const int64_t ggrid64 = (static_cast<int64_t>(n) * kG + 255) / 256;
+  BLK_REQUIRE(ggrid64 <= INT32_MAX, BLKAMG_EINVAL, "too many vertices");
+  const int ggrid = static_cast<int>(ggrid64);
+  mis_init_kernel<<<grid, 256, 0, s>>>(n, d_dirichlet, seed, key, state);
   HIP_CHECK(hipGetLastError());
   int32_t rounds = 0, left = n;
   while (left > 0) {
     BLK_REQUIRE(rounds < n, BLKAMG_EINVAL, "aggregation rounds did not finish");
     ++rounds;
-    mis_max1_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, key.p, state.p, m1.p);
-    mis_select_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, key.p, m1.p, state.p);
-    mis_near_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, state.p, near.p);
-    mis_zero_kernel<<<1, 64, 0, s>>>(counter.p);
-    mis_decide_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, near.p, state.p, counter.p);
+    mis_max1_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, key, state, m1);
+    mis_select_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, key, m1, state);
+    mis_near_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, state, near);
+    mis_zero_kernel<<<1, 64, 0, s>>>(counter);
+    mis_decide_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, near, state, counter);
     HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipMemcpyAsync(&left, counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&left, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
   }
-  mis_root_flag_kernel<<<grid, 256, 0, s>>>(n, state.p, flag.p);
+  mis_root_flag_kernel<<<grid, 256, 0, s>>>(n, state, flag);
   HIP_CHECK(hipGetLastError());
-  size_t tmp_bytes = 0;
-  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, flag.p, root_id.p, n, s));
-  DevBuf<char> tmp(std::max<size_t>(tmp_bytes, 1));
-  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, flag.p, root_id.p, n, s));
-  mis_phase1_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, state.p, root_id.p, agg1.p);
-  mis_phase2_kernel<<<grid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, agg1.p, d_agg);
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, flag, root_id, n, s));
+  mis_phase1_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, state, root_id, agg1);
+  mis_phase2_kernel<<<ggrid, 256, 0, s>>>(n, A->rowptr, A->colidx, d_dirichlet, agg1, d_agg);
   HIP_CHECK(hipGetLastError());
   int32_t last_id = 0, last_flag = 0;
-  HIP_CHECK(hipMemcpyAsync(&last_id, root_id.p + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&last_flag, flag.p + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&last_id, root_id + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&last_flag, flag + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   *n_agg = last_id + last_flag;
   if (n_rounds) *n_rounds = rounds;
