@@ -50,8 +50,10 @@ __global__ void mis_init_kernel(int32_t n, const uint8_t* __restrict__ dir, uint
 
 // The passes over the graph give each vertex a group of kG lanes that stride over its
 // neighbours (consecutive lanes read consecutive column indices) and combine their
-// findings by shuffles; lane 0 of the group writes the vertex's result.
-constexpr int kG = 32;
+// findings by shuffles; lane 0 of the group writes the vertex's result.  Eight lanes
+// (27 neighbours: four trips) keep the number of waves, which bounds these light
+// passes, at a quarter of what 32 lanes would launch.
+constexpr int kG = 8;
 
 __device__ __forceinline__ uint64_t group_max(uint64_t v) {
 #pragma unroll
@@ -131,10 +133,16 @@ __global__ void mis_near_kernel(int32_t n, const int32_t* __restrict__ rp, const
 }
 
 // pass 4: decide the undecided vertices within distance 2 of a new root, promote the
-// new roots, count what stays undecided
-__global__ void mis_decide_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                  const uint8_t* __restrict__ dir, const uint8_t* __restrict__ near,
-                                  uint8_t* __restrict__ state, int32_t* __restrict__ n_undecided) {
+// new roots, count what stays undecided (summed per workgroup in LDS, then one global
+// atomic per workgroup)
+__global__ __launch_bounds__(256) void mis_decide_kernel(int32_t n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci,
+                                                         const uint8_t* __restrict__ dir,
+                                                         const uint8_t* __restrict__ near, uint8_t* __restrict__ state,
+                                                         int32_t* __restrict__ n_undecided) {
+  __shared__ int32_t block_left;
+  if (threadIdx.x == 0) block_left = 0;
+  __syncthreads();
   const GroupRow r = group_row(n);
   const uint8_t s = r.active ? state[r.i] : kOut;
   uint64_t hit = 0;
@@ -146,13 +154,16 @@ __global__ void mis_decide_kernel(int32_t n, const int32_t* __restrict__ rp, con
     }
   }
   hit = group_max(hit);
-  if (r.lane != 0) return;
-  if (s == kNewRoot) {
-    state[r.i] = kRoot;
-  } else if (s == kUndecided) {
-    if (hit) state[r.i] = kOut;
-    else atomicAdd(n_undecided, 1);
+  if (r.lane == 0) {
+    if (s == kNewRoot) {
+      state[r.i] = kRoot;
+    } else if (s == kUndecided) {
+      if (hit) state[r.i] = kOut;
+      else atomicAdd(&block_left, 1);
+    }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && block_left > 0) atomicAdd(n_undecided, block_left);
 }
 
 __global__ void mis_zero_kernel(int32_t* __restrict__ c) {
