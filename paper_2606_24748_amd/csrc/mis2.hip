@@ -39,13 +39,24 @@ __device__ __forceinline__ bool free_vertex(const uint8_t* __restrict__ dir, int
   return dir == nullptr || dir[v] == 0;
 }
 
-__global__ void mis_init_kernel(int32_t n, const uint8_t* __restrict__ dir, uint64_t seed, uint64_t* __restrict__ key,
-                                uint8_t* __restrict__ state) {
+// priorities and states; the free (undecided) vertices are counted per workgroup in
+// LDS, then with one global atomic per workgroup
+__global__ __launch_bounds__(256) void mis_init_kernel(int32_t n, const uint8_t* __restrict__ dir, uint64_t seed,
+                                                       uint64_t* __restrict__ key, uint8_t* __restrict__ state,
+                                                       int32_t* __restrict__ n_undecided) {
+  __shared__ int32_t block_free;
+  if (threadIdx.x == 0) block_free = 0;
+  __syncthreads();
   const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= n) return;
-  const uint64_t h = mix64(seed ^ static_cast<uint64_t>(i));
-  key[i] = ((h >> 32) << 32) | static_cast<uint64_t>(i + 1);
-  state[i] = free_vertex(dir, i) ? kUndecided : kOut;
+  if (i < n) {
+    const uint64_t h = mix64(seed ^ static_cast<uint64_t>(i));
+    key[i] = ((h >> 32) << 32) | static_cast<uint64_t>(i + 1);
+    const bool f = free_vertex(dir, i);
+    state[i] = f ? kUndecided : kOut;
+    if (f) atomicAdd(&block_free, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && block_free > 0) atomicAdd(n_undecided, block_free);
 }
 
 // The passes over the graph give each vertex a group of kG lanes that stride over its
@@ -282,9 +293,12 @@ int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int3
   const int64_t ggrid64 = (static_cast<int64_t>(n) * kG + 255) / 256;
   BLK_REQUIRE(ggrid64 <= INT32_MAX, BLKAMG_EINVAL, "too many vertices");
   const int ggrid = static_cast<int>(ggrid64);
-  mis_init_kernel<<<grid, 256, 0, s>>>(n, d_dirichlet, seed, key, state);
+  mis_zero_kernel<<<1, 64, 0, s>>>(counter);
+  mis_init_kernel<<<grid, 256, 0, s>>>(n, d_dirichlet, seed, key, state, counter);
   HIP_CHECK(hipGetLastError());
-  int32_t rounds = 0, left = n;
+  int32_t rounds = 0, left = 0;
+  HIP_CHECK(hipMemcpyAsync(&left, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
   while (left > 0) {
     BLK_REQUIRE(rounds < n, BLKAMG_EINVAL, "aggregation rounds did not finish");
     ++rounds;

@@ -115,3 +115,25 @@ def test_fe_plan_errors():
     with pytest.raises(ValueError):
         B.fe_q1_stream(torch.as_tensor(bad).cuda().int(), d["X"], d["lam"], d["mu"],
                        torch.empty(m.n_elem * 64 * 9, dtype=torch.float64, device="cuda"))
+
+
+def test_fe_empty_inputs():
+    """No elements: the stream holds only the identity tail, and element-by-element
+    assembly leaves zeros plus the flagged identity blocks."""
+    en = torch.zeros((0, 8), dtype=torch.int32, device="cuda")
+    X = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    out = torch.full((5, 3, 3), 7.0, dtype=torch.float64, device="cuda")
+    B.fe_q1_stream(en, X, z, z, out, n_identity=5)
+    assert torch.equal(out.cpu(), torch.eye(3, dtype=torch.float64).expand(5, 3, 3))
+    nn = 4
+    rp = torch.arange(nn + 1, dtype=torch.int32, device="cuda")
+    ci = torch.arange(nn, dtype=torch.int32, device="cuda")
+    v = torch.full((nn * 9,), 3.0, dtype=torch.float64, device="cuda")
+    H = B.bsr_create(nn, nn, 3, 3, rp, ci, v)
+    P = B.fe_ebe_plan_create(H, np.zeros((0, 8), dtype=np.int32), np.array([1, 0, 0, 1], dtype=np.uint8))
+    assert P.info()["n_colors"] == 0
+    B.fe_q1_assemble_ebe(P, H, en, X, z, z, B.FE_COLORED)
+    got = v.view(nn, 3, 3).cpu()
+    assert torch.equal(got[0], torch.eye(3, dtype=torch.float64)) and torch.equal(got[3], torch.eye(3, dtype=torch.float64))
+    assert not torch.any(got[1:3])

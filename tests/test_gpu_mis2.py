@@ -84,3 +84,20 @@ def test_luby_option_errors():
     o.agg_mode = 7
     with pytest.raises(B.BlkAmgError):
         B.amg_setup(HA, m.coords, m.dirichlet, o)
+
+
+def test_device_aggregation_degenerate_graphs():
+    """Isolated vertices are their own roots after one round; a fully flagged graph has no
+    aggregates and takes no round; both as the oracle says."""
+    n = 37
+    rp = torch.arange(n + 1, dtype=torch.int32, device="cuda")
+    ci = torch.arange(n, dtype=torch.int32, device="cuda")
+    v = torch.ones(n * 9, dtype=torch.float64, device="cuda")
+    H = B.bsr_create(n, n, 3, 3, rp, ci, v)
+    A = S.Bsr(n, n, 3, 3, np.arange(n + 1), np.arange(n), np.ones((n, 3, 3)))
+    for d in (np.zeros(n, dtype=bool), np.arange(n) % 5 == 0, np.ones(n, dtype=bool)):
+        agg, n_agg, rounds = B.sa_aggregate_device(H, d)
+        want, n_want, r_want = sa.aggregate_luby(sa.strength_graph(A, d), d)
+        assert (n_agg, rounds) == (n_want, r_want)
+        assert np.array_equal(agg.cpu().numpy(), want)
+    assert n_agg == 0 and rounds == 0
