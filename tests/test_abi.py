@@ -132,3 +132,21 @@ def test_set_allocator_arguments():
         B.blkamg_set_allocator(None, lambda p, n, c: None)
     B.blkamg_set_allocator(lambda n, c: None, lambda p, n, c: None)
     B.blkamg_set_allocator()
+
+
+def test_new_wrappers_reject_bad_arguments_on_the_host():
+    """Argument checks of the FE, aggregation and hierarchy wrappers run before any
+    device work (CPU tensors, shape mismatches, missing prolongators)."""
+    torch = pytest.importorskip("torch")
+    en = torch.zeros((2, 8), dtype=torch.int32)
+    X = torch.zeros((8, 3), dtype=torch.float64)
+    lm = torch.ones(2, dtype=torch.float64)
+    with pytest.raises(ValueError):  # host tensors
+        B.fe_q1_stream(en, X, lm, lm, torch.zeros(2 * 64 * 9, dtype=torch.float64))
+    with pytest.raises(ValueError):  # len(P) must be len(A) - 1
+        B.amg_hierarchy_create([object(), object()], [])
+    with pytest.raises(B.BlkAmgError):  # NULL matrix handle
+        B._check(B._lib.sa_aggregate_device(None, None, 0, None, B.C.byref(B._i32()), None, None),
+                 "sa_aggregate_device")
+    with pytest.raises(B.BlkAmgError):
+        B._check(B._lib.fe_ebe_plan_create(None, 0, None, None, B.C.byref(B._p())), "fe_ebe_plan_create")
