@@ -289,7 +289,8 @@ def run_q2(args, B, RL, torch, dev, stream):
     log(f"[q2] coo plan: nnzb={a_inf['nnzb']} ({t_plan:.1f}s)")
     res = {"n": n, "dofs": mesh.n_dof, "fine_nnzb": a_inf["nnzb"],
            "scalar_nnz_per_row": a_inf["nnzb"] * 9 / mesh.n_dof, "coo_plan_s": t_plan}
-    for var in ("mixed", "fp64"):
+    variants = () if args.probe_only else ("mixed", "fp64")  # --probe-only: the SpMV probe alone (counters)
+    for var in variants:
         r = run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b, tag=f"q2/{var}")
         r.pop("_x", None)
         res[var] = r
@@ -297,7 +298,7 @@ def run_q2(args, B, RL, torch, dev, stream):
     probe["frac"] = probe["achieved_GBs"] / RL.HBM_PEAK_GBS
     res["spmv"] = probe
     log(f"[q2] fine SpMV {probe['avg_launch_ms']:.3f} ms, {probe['achieved_GBs']:.0f} GB/s "
-        f"({100 * probe['frac']:.1f}% of HBM peak); mixed PCG+PtAP {res['mixed']['pcg_plus_ptap_s']:.4f} s")
+        f"({100 * probe['frac']:.1f}% of HBM peak)")
     del plan, HA, vals
     torch.cuda.synchronize()
     return res
