@@ -269,7 +269,7 @@ def run_q2(args, B, RL, torch, dev, stream):
     """Triquadratic (Q2, 27-node) elasticity at q2_n^3 elements: as many dofs as the Q1
     problem with twice the edge (64^3 Q2 and 128^3 Q1 both have 6,440,067 dofs), with
     block rows of 27 to 125 blocks instead of at most 27 (the nonzeros-per-row study of
-    paper §5, Table 4).  Same material and right-hand-side seeds and the same hot path
+    paper §4.6, Table 4).  Same material and right-hand-side seeds and the same hot path
     as the Q1 workload; mixed and FP64 hierarchies, then the fine FP64 SpMV probe."""
     import synth
 

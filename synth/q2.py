@@ -1,6 +1,6 @@
 """Q2 (triquadratic, 27-node hexahedral) variant of the elasticity model problem.
 
-The paper's sensitivity study (§5, Table 4) sets the trilinear discretisation (about
+The paper's sensitivity study (§4.6, Table 4) sets the trilinear discretisation (about
 78 nonzeros per row) against the triquadratic one (about 180) at matched total
 degrees of freedom.  This module generates the triquadratic problem with the same
 unit cube, materials, clamped x = 0 face and COO stream layout as the Q1 generator:

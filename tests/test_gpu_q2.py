@@ -1,5 +1,5 @@
 """GPU parity on the triquadratic (Q2, 27-node) elasticity problem: block rows of 27 to
-125 blocks instead of at most 27 (the nonzeros-per-row study of paper §5, Table 4)."""
+125 blocks instead of at most 27 (the nonzeros-per-row study of paper §4.6, Table 4)."""
 import numpy as np
 import pytest
 

@@ -130,3 +130,70 @@ def test_recompute_matches_fresh_galerkin_on_fixed_p():
         assert np.array_equal(L.A.val, L3.A.val)
         if L.lam is not None:
             assert L.lam == L3.lam
+
+
+def _smoother_error_operator(A, lam, degree=2, lo=0.1, hi=1.1):
+    """Dense error propagation of the Chebyshev / point-block-Jacobi smoother,
+    p_k(D^-1 A), from the eigen-decomposition of the pencil (A, D), where D is the
+    block diagonal of A taken straight from the stored blocks."""
+    Ad, Dd = S.to_dense(A), _dense_D(A)
+    w, W = sla.eigh(Ad, Dd)
+    a, b = lo * lam, hi * lam
+    T = np.polynomial.chebyshev.Chebyshev.basis(degree)
+    p = T((b + a - 2 * w) / (b - a)) / T((b + a) / (b - a))
+    return W @ np.diag(p) @ W.T @ Dd
+
+
+def _vcycle_matrix(H):
+    n = H.levels[0].A.nbr * H.levels[0].A.br
+    return np.column_stack([solve.vcycle(H, e) for e in np.eye(n)])
+
+
+def _two_grid_inverse(A, lam, P, coarse_inv):
+    """M = (I - S (I - P C P^T A) S) A^-1 with S the smoother's error operator and C the
+    coarse-level approximate inverse: the error propagation of pre-smoothing, coarse
+    correction and post-smoothing (paper §2.1), composed densely."""
+    Ad, Pd = S.to_dense(A), S.to_dense(P)
+    Sm = _smoother_error_operator(A, lam)
+    n = Ad.shape[0]
+    E = Sm @ (np.eye(n) - Pd @ coarse_inv @ Pd.T @ Ad) @ Sm
+    return (np.eye(n) - E) @ np.linalg.inv(Ad), E
+
+
+def test_vcycle_two_level_error_propagation():
+    """I - M A = S (I - P A_c^-1 P^T A) S on a two-level hierarchy (paper §2.1), with
+    A_c = P^T A P formed densely and S the closed-form Chebyshev error operator.
+    Dropping the coarse-grid correction or flipping its sign breaks this identity."""
+    m, A = _problem(4, seed=9)
+    H = solve.setup(A, m.coords, m.dirichlet, solve.Options(coarse_eq_limit=100))
+    assert H.n_levels == 2
+    L0 = H.levels[0]
+    Pd = S.to_dense(L0.P)
+    Ac = Pd.T @ S.to_dense(A) @ Pd
+    _, E_want = _two_grid_inverse(A, L0.lam, L0.P, np.linalg.inv(Ac))
+    Mg = _vcycle_matrix(H)
+    E_got = np.eye(Mg.shape[0]) - Mg @ S.to_dense(A)
+    assert np.abs(E_got - E_want).max() <= 1e-10 * max(1.0, np.abs(E_want).max())
+    # the coarse correction is not the identity: without it the operator is S^2
+    Sm = _smoother_error_operator(A, L0.lam)
+    assert np.abs(E_got - Sm @ Sm).max() > 1e-3
+
+
+def test_vcycle_three_level_error_propagation():
+    """Three levels: the level-0 coarse correction uses the level-1 V-cycle as its
+    approximate inverse, M_1 = (I - S_1 (I - P_1 A_2^-1 P_1^T A_1) S_1) A_1^-1."""
+    m, A = _problem(6, seed=10)
+    H = solve.setup(A, m.coords, m.dirichlet, solve.Options(coarse_eq_limit=60))
+    assert H.n_levels == 3
+    L0, L1 = H.levels[0], H.levels[1]
+    P0, P1 = S.to_dense(L0.P), S.to_dense(L1.P)
+    A1 = P0.T @ S.to_dense(A) @ P0
+    A2 = P1.T @ A1 @ P1
+    # the level-1 operator the oracle stores is the Galerkin product (checked elsewhere);
+    # the smoother's closed form on level 1 uses it
+    assert np.abs(S.to_dense(L1.A) - A1).max() <= 1e-12 * np.abs(A1).max()
+    M1, _ = _two_grid_inverse(L1.A, L1.lam, L1.P, np.linalg.inv(A2))
+    _, E_want = _two_grid_inverse(A, L0.lam, L0.P, M1)
+    Mg = _vcycle_matrix(H)
+    E_got = np.eye(Mg.shape[0]) - Mg @ S.to_dense(A)
+    assert np.abs(E_got - E_want).max() <= 1e-9 * max(1.0, np.abs(E_want).max())
