@@ -12,18 +12,21 @@ One step = one pass of the hot path on fresh operator values: blocked COO assemb
 the fine operator, Galerkin recompute A_c = P^T A P on every level (fixed patterns,
 reused prolongators), smoother refresh (block-diagonal inverses, Lanczos estimates,
 coarsest Cholesky), and the PCG solve.  Values alternate between two material draws,
-so every step really recomputes.  Two hierarchies are timed: "mixed" (V-cycle
-hierarchy in FP32 with FP32 accumulation; FP64 PCG, fine residual SpMV and coarsest
-Cholesky) and "fp64".  The reported value is PCG solve seconds + PtAP recompute
-seconds of the mixed hierarchy (median over the timed steps); the FP64 figures are
-reported beside it.
+so every step really recomputes.  Hierarchies timed: "fp64" (everything in FP64, the
+paper's arithmetic) and the mixed variants (V-cycle hierarchy in FP32 with FP32
+accumulation, optionally BF16 prolongators, the learned eigenbound or device
+aggregation; FP64 PCG, fine residual SpMV and coarsest Cholesky).  The reported value
+is PCG solve seconds + PtAP recompute seconds of the FP64 hierarchy (median over the
+timed steps); the mixed figures and their speed-up are reported beside it.
 
 Also reported: the HBM roofline of the fine 3x3 FP64 SpMV (bsr_spmv) measured with
-HIP events, the Galerkin recompute's algorithmic bandwidth, and the CPU oracle timed
-on this host on a bounded sample (see cpu_baseline.sample).  Side sections (not the
-value): the learned eigenbound at 96^3, a batch of 24 instances with 8 right-hand
-sides, and the triquadratic (Q2, 27-node) problem at 64^3 elements, which has the
-same dofs as the Q1 workload but about 2.4 times the blocks.
+HIP events, the Galerkin recompute's algorithmic bandwidth (ptap_roofline), and the
+CPU oracle measured on this host on the 64^3 problem (one core, in a child process
+while the GPU sections run), with the GPU's own time on that problem beside it.  The
+last stdout line is the compact result; per-step records and the side sections (the
+learned eigenbound at 96^3, a batch of 24 instances with 8 right-hand sides, the
+triquadratic (Q2, 27-node) problem at 64^3 elements, finite-element assembly) go to
+stderr as one "[bench] detail" JSON line and, with --detail-out, to a file.
 """
 from __future__ import annotations
 
@@ -94,24 +97,35 @@ def parse_args(argv=None):
     ap.add_argument("--fe-n", type=int, default=128, help="elements per edge of the FE assembly problem")
     ap.add_argument("--fe-scalar-n", type=int, default=64,
                     help="elements per edge of the blocked vs scalar COO comparison")
-    ap.add_argument("--only-section", choices=("learned", "batch", "q2", "fe"), default=None,
+    ap.add_argument("--only-section", choices=("learned", "batch", "q2", "fe", "ptap"), default=None,
                     help="run only that section and print its result (profiling runs)")
     ap.add_argument("--learned-n", type=int, default=96, help="edge of the learned-eigenbound deployment problem")
     ap.add_argument("--model", default=None, help="eigenbound model JSON (default: the packaged one)")
     ap.add_argument("--batch-eager", action="store_true",
                     help="also time the batched CG launched eagerly (no graph replay)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--cpu-n", type=int, default=32, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-n", type=int, default=CPU_N, help="elements per edge of the oracle's CPU baseline problem")
+    ap.add_argument("--no-config-s", action="store_true", help="skip the 64^3 FP64 section (the CPU baseline's problem)")
+    ap.add_argument("--detail-out", default=None,
+                    help="also write the full result (per-step records, side sections) to this JSON file")
     return ap.parse_args(argv)
 
 
 # ----------------------------------------------------------------------------------
-# CPU baseline: the oracle, single core, on a bounded sample (run in a child process)
+# CPU baseline: the oracle, one core, on the 64^3 problem (run in a child process that
+# works while the GPU sections run)
 # ----------------------------------------------------------------------------------
+CPU_N = 64               # Q1 elasticity at 64^3 elements (823,875 dofs), 4-level hierarchy
+CPU_SEEDS = (1, 1001, 2)  # materials, redrawn materials, right-hand side
+
+
 def cpu_baseline_child(n: int) -> dict:
+    """The oracle's hot path on one core: cold setup on the first material draw
+    (untimed), then, on the redrawn materials, the Galerkin recompute over all levels
+    and the PCG solve to 1e-8 with the V-cycle of the recomputed hierarchy (timed)."""
     try:
         cpus = sorted(os.sched_getaffinity(0))
-        os.sched_setaffinity(0, {cpus[0]})
+        os.sched_setaffinity(0, {cpus[-1]})
     except (AttributeError, OSError):
         pass
     import numpy as np
@@ -120,10 +134,11 @@ def cpu_baseline_child(n: int) -> dict:
     from oracle import solve
     from oracle import sparse as S
 
+    s0, s1, sb = CPU_SEEDS
     m = synth.make_mesh(n)
     i, j = synth.coo_indices(m)
-    v0 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 11)))
-    v1 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 1011)))
+    v0 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, s0)))
+    v1 = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, s1)))
     A0 = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v0)
     H = solve.setup(A0, m.coords, m.dirichlet)
     t0 = time.perf_counter()
@@ -135,28 +150,47 @@ def cpu_baseline_child(n: int) -> dict:
         A = S.ptap(A, L.P)
     t_ptap = time.perf_counter() - t0
     H1 = solve.recompute(H, A1)
-    b = synth.rhs(m, 12)
+    b = synth.rhs(m, sb)
     t0 = time.perf_counter()
     _, its, rel, ok = solve.pcg(A1, b, lambda r: solve.vcycle(H1, r), rtol=1e-8)
     t_pcg = time.perf_counter() - t0
-    return {"n": n, "nnzb": int(A1.nnzb), "coo_s": t_coo, "ptap_s": t_ptap, "pcg_s": t_pcg, "pcg_its": its,
-            "converged": bool(ok), "relres": rel, "host_cpus": os.cpu_count()}
+    return {"n": n, "dofs": int(m.n_dof), "nnzb": int(A1.nnzb), "levels": [int(L.A.nbr * L.A.br) for L in H.levels],
+            "coo_s": t_coo, "ptap_s": t_ptap, "pcg_s": t_pcg, "pcg_its": its, "converged": bool(ok),
+            "relres": rel, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
-def run_cpu_baseline(n: int) -> dict | None:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def start_cpu_baseline(n: int):
+    """Start the oracle child process (one thread, numerical libraries single-threaded)."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
         env[k] = "1"
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-n", str(n)]
+    return subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc, timeout: float = 600.0) -> dict | None:
     try:
-        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=300)
+        out, err = proc.communicate(timeout=timeout)
     except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
         log("cpu baseline timed out")
         return None
-    if r.returncode != 0:
-        log("cpu baseline failed: " + r.stderr[-2000:])
+    if proc.returncode != 0:
+        log("cpu baseline failed: " + err[-2000:])
         return None
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    return json.loads(out.strip().splitlines()[-1])
 
 
 # ----------------------------------------------------------------------------------
@@ -498,10 +532,8 @@ def run_learned(args, B, torch, dev, stream):
     return res
 
 
-def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b, tag=None):
-    """Set up one hierarchy variant on the assembled operator and time the hot path
-    (assembly, Galerkin recompute, refresh, PCG) over warmup + steps passes."""
-    tag = tag or var
+def variant_opts(B, var):
+    """Setup options of a hierarchy variant."""
     o = B.blkamg_opts_default()
     if var == "fp64":
         o.hier_dtype, o.p_dtype = B.F64, B.F64
@@ -515,6 +547,14 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
         o.hier_dtype, o.p_dtype, o.agg_mode = B.F32, B.F32, B.AGG_LUBY
     else:
         raise SystemExit(f"unknown variant {var}")
+    return o
+
+
+def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b, tag=None):
+    """Set up one hierarchy variant on the assembled operator and time the hot path
+    (assembly, Galerkin recompute, refresh, PCG) over warmup + steps passes."""
+    tag = tag or var
+    o = variant_opts(B, var)
     B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -570,8 +610,6 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
     for l in range(nl - 1):
         d, c = lev[l], lev[l + 1]
         ptap_bytes += RL.ptap_bytes(d["nbr"], d["nnzb"], d["bs"], d["p_nnzb"], 6, c["nbr"], c["nnzb"], vsz, psz)
-    if o.hier_dtype != B.F64:
-        ptap_bytes += a_inf["nnzb"] * 9 * (8 + 4)  # cast of the fine operator to the F32 copy
     res = {
         "setup_s": t_setup, "levels": lev, "steps": rec, "median_ms": med,
         "pcg_plus_ptap_s": (med["pcg_ms"] + med["ptap_ms"]) / 1e3,
@@ -592,6 +630,68 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
     return res
 
 
+def run_config_s(args, B, RL, torch, dev, stream):
+    """The 64^3 FP64 problem the CPU baseline runs (823,875 dofs, materials seed 1,
+    redraw 1001, right-hand side seed 2): the same hot path on the GPU, so the oracle's
+    time has a like-for-like GPU figure beside it."""
+    import synth
+
+    n = args.cpu_n
+    s0, s1, sb = CPU_SEEDS
+    mesh = synth.make_mesh(n)
+    ii, jj = synth.coo_indices(mesh)
+    vals = [synth.coo_values_torch(mesh, *synth.lame(*synth.materials(mesh.n_elem, sd)), dev) for sd in (s0, s1)]
+    b = torch.as_tensor(synth.rhs(mesh, sb), device=dev)
+    plan, HA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, ii, jj)
+    del ii, jj
+    r = run_variant(args, B, RL, torch, dev, stream, "fp64", mesh, plan, HA, HA.info(), vals, b, tag=f"S{n}/fp64")
+    r.pop("_x", None)
+    r["n"], r["dofs"] = n, mesh.n_dof
+    del plan, HA, vals
+    torch.cuda.synchronize()
+    return r
+
+
+def run_ptap_only(args, B, RL, torch, dev, stream):
+    """Galerkin recompute alone (for counter runs): the fine operator at n^3, the first
+    hierarchy variant, then `steps` recomputes on alternating material draws."""
+    import synth
+
+    n = args.n
+    mesh = synth.make_mesh(n)
+    ii, jj = synth.coo_indices(mesh)
+    vals = [synth.coo_values_torch(mesh, *synth.lame(*synth.materials(mesh.n_elem, sd)), dev) for sd in (11, 1011)]
+    plan, HA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, ii, jj)
+    del ii, jj
+    var = [v.strip() for v in args.variants.split(",") if v.strip()][0]
+    o = variant_opts(B, var)
+    B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
+    M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
+    ms = []
+    for s in range(args.warmup + args.steps):
+        B.coo_assemble_blocked(plan, vals[(s + 1) % 2], B.INSERT, HA)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.amg_galerkin_recompute(M)
+        e1.record(stream)
+        e1.synchronize()
+        if s >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+        log(f"[ptap/{var}] step {s}: {e0.elapsed_time(e1):.3f} ms")
+    return {"variant": var, "n": n, "ptap_ms": ms, "median_ms": statistics.median(ms) if ms else None}
+
+
+def _ptap_roofline(RL, r):
+    """Galerkin recompute over all levels against the HBM roofline: the algorithmic bytes
+    of the recompute (A and P read once, A_c written once, int32 indices; no cast of the
+    fine operator) over the median recompute time."""
+    ms = r["median_ms"]["ptap_ms"]
+    ach = r["ptap_alg_bytes"] / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / RL.HBM_PEAK_GBS,
+            "traffic": None, "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
+            "median_ms": ms}
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.cpu_baseline_only:
@@ -601,7 +701,7 @@ def main(argv=None):
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this solve-phase build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     import synth
@@ -617,11 +717,17 @@ def main(argv=None):
             result = run_q2(args, B, RL, torch, dev, stream)
         elif args.only_section == "fe":
             result = run_fe(args, B, torch, dev, stream)
+        elif args.only_section == "ptap":
+            result = run_ptap_only(args, B, RL, torch, dev, stream)
         else:
             run = run_learned if args.only_section == "learned" else run_batch
             result = run(args, B, torch, dev, stream)
         print(json.dumps({"section": args.only_section, "result": result}))
         return 0
+    cpu_proc = None
+    if not args.no_cpu_baseline and not args.probe_only:
+        log(f"cpu baseline started (oracle, 1 core, {args.cpu_n}^3)")
+        cpu_proc = start_cpu_baseline(args.cpu_n)
     n = args.n
     t_all = time.perf_counter()
     mesh = synth.make_mesh(n)
@@ -650,69 +756,87 @@ def main(argv=None):
         results[var] = run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, vals, b)
 
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
+    copy = copy_probe(torch, stream)
     aggregation = run_aggregation(B, torch, HA, mesh.dirichlet)
-    batch = None
-    learned = None
-    q2 = None
-    fe = None
+    side = {}
     del plan, HA, vals
     torch.cuda.empty_cache()
+    if not args.no_config_s:
+        side["config_s"] = run_config_s(args, B, RL, torch, dev, stream)
+        torch.cuda.empty_cache()
     if not args.no_fe:
-        fe = run_fe(args, B, torch, dev, stream)
+        side["fe"] = run_fe(args, B, torch, dev, stream)
         torch.cuda.empty_cache()
     if not args.no_q2:
-        q2 = run_q2(args, B, RL, torch, dev, stream)
+        side["q2"] = run_q2(args, B, RL, torch, dev, stream)
         torch.cuda.empty_cache()
     if not args.no_learned:
-        learned = run_learned(args, B, torch, dev, stream)
+        side["learned"] = run_learned(args, B, torch, dev, stream)
         torch.cuda.empty_cache()
     if not args.no_batch:
-        batch = run_batch(args, B, torch, dev, stream)
+        side["batch"] = run_batch(args, B, torch, dev, stream)
     achieved, spmv_b, spmv_ms = probe["achieved_GBs"], probe["bytes_per_launch"], probe["avg_launch_ms"]
 
-    head = "mixed" if "mixed" in results else variants[0]
+    head = "fp64" if "fp64" in results else variants[0]
     hr = results[head]
     cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, 1 core)")
-        cb = run_cpu_baseline(args.cpu_n)
+    if cpu_proc is not None:
+        log("waiting for the cpu baseline")
+        cb = finish_cpu_baseline(cpu_proc)
         if cb:
-            scale = a_inf["nnzb"] / cb["nnzb"]
-            gpu_its = statistics.median(hr["iterations"])
-            est = cb["ptap_s"] * scale + cb["pcg_s"] / max(cb["pcg_its"], 1) * gpu_its * scale
-            cpu = {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-                   "sample": (f"oracle (numpy/scipy FP64) on the {cb['n']}^3 instance of the same problem family "
-                              f"(nnzb {cb['nnzb']}): PtAP recompute {cb['ptap_s']:.2f} s, PCG {cb['pcg_s']:.2f} s "
-                              f"for {cb['pcg_its']} its; scaled linearly by fine nnzb (x{scale:.1f}) and to "
-                              f"{gpu_its} iterations"),
-                   "measured": cb}
+            cs = side.get("config_s")
+            gpu_s = cs["pcg_plus_ptap_s"] if cs else None
+            cpu = {"value": cb["ptap_s"] + cb["pcg_s"], "unit": "s", "cores": 1, "kind": "oracle",
+                   "sample": (f"oracle (numpy/scipy, FP64) on one core of this host ({cb['cpu_model']}): Q1 "
+                              f"elasticity {cb['n']}^3 elements ({cb['dofs']} dofs, levels {cb['levels']}), PtAP "
+                              f"recompute over all levels {cb['ptap_s']:.1f} s + PCG to 1e-8 {cb['pcg_s']:.1f} s "
+                              f"({cb['pcg_its']} its); measured once, not scaled to {n}^3"),
+                   "workload_n": cb["n"], "gpu_fp64_same_workload_s": gpu_s,
+                   "gpu_speedup_same_workload": (cb["ptap_s"] + cb["pcg_s"]) / gpu_s if gpu_s else None,
+                   "pcg_its_oracle": cb["pcg_its"],
+                   "pcg_its_gpu": (statistics.median(cs["iterations"]) if cs else None)}
+            side["cpu_baseline_measured"] = cb
     for v in results.values():
         v.pop("_x", None)
     value = hr["pcg_plus_ptap_s"]
     out = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": hr["ms_per_step"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if head.startswith("mixed") else "f64", "data": "synthetic",
+        "dtype": "f64" if head == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"Q1 elasticity {n}^3 elements ({mesh.n_dof} dofs), lognormal E, "
                                f"{len(hr['levels'])}-level SA, Chebyshev(2) V-cycle PCG to 1e-8",
                    "n": n, "dofs": mesh.n_dof, "variant": head},
+        "pcg_ms": hr["median_ms"]["pcg_ms"], "ptap_ms": hr["median_ms"]["ptap_ms"],
+        "pcg_its": statistics.median(hr["iterations"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / RL.HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "bsr_spmv fine 3x3 f64 (spmv_kernel<3,3,1,32,double,double,double,EpiAxpby>)",
+                     "kernel": "bsr_spmv fine 3x3 f64 (spmv_kernel<3,3,1,32,1,double,double,double,EpiAxpby>)",
                      "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
+        "ptap_roofline": _ptap_roofline(RL, hr),
+        "copy_GBs": copy["GBs"],
         "cpu_baseline": cpu,
-        "variants": results,
-        "batch": batch,
-        "learned": learned,
-        "q2": q2,
-        "fe": fe,
-        "aggregation": aggregation,
-        "coo_plan_s": t_plan,
     }
-    if "fp64" in results and head != "fp64":
-        out["fp64_value"] = results["fp64"]["pcg_plus_ptap_s"]
-        out["mixed_speedup_vs_fp64"] = results["fp64"]["pcg_plus_ptap_s"] / value
-    print(json.dumps(out))
+    alt = {}
+    for var, r in results.items():
+        if var == head:
+            continue
+        alt[var] = {"value": r["pcg_plus_ptap_s"], "pcg_ms": r["median_ms"]["pcg_ms"],
+                    "ptap_ms": r["median_ms"]["ptap_ms"], "pcg_its": statistics.median(r["iterations"]),
+                    "speedup_vs_head": value / r["pcg_plus_ptap_s"]}
+        if var == "mixed":
+            alt[var]["ptap_roofline_frac"] = _ptap_roofline(RL, r)["frac"]
+    out["variants"] = alt
+    if "mixed" in results and head == "fp64":
+        out["mixed_value"] = results["mixed"]["pcg_plus_ptap_s"]
+        out["mixed_speedup_vs_fp64"] = value / results["mixed"]["pcg_plus_ptap_s"]
+    detail = {"variants": results, "spmv_probe": probe, "copy": copy, "aggregation": aggregation,
+              "coo_plan_s": t_plan, **side}
+    line = json.dumps(detail)
+    print("[bench] detail " + line, file=sys.stderr, flush=True)
+    if args.detail_out:
+        with open(args.detail_out, "w") as f:
+            f.write(line + "\n")
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -162,6 +162,29 @@ def dtype_code(t) -> int:
     return _DT[str(t.dtype).replace("torch.", "")]
 
 
+def _dev_tensor(t, numel, dtypes, name):
+    """Host-side check of a tensor handed to a kernel as a raw device pointer: a
+    contiguous device tensor of one of `dtypes` with exactly `numel` elements.  A CPU
+    tensor, a short vector or the wrong element type would otherwise make the kernel
+    read or write out of bounds."""
+    if t is None or not hasattr(t, "data_ptr"):
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype_code(t) not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {[str(_torch_dtype(d)) for d in dtypes]}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _vec_dtypes(mat_dtype):
+    """Vector types a matrix of `mat_dtype` is applied to: F64 with F64 matrices, F32
+    with F32 and BF16 matrices."""
+    return (F64,) if mat_dtype == F64 else (F32,)
+
+
 def _torch_dtype(code):
     import torch
     return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[code]
@@ -178,6 +201,14 @@ class Bsr:
         self._keep = keep
         self._destroy = owned_by_lib and owner is None
         self._owner = owner
+        self._shape = None
+
+    def shape_info(self):
+        """(nbr, nbc, bs_r, bs_c, dtype): fixed for the life of the handle, cached."""
+        if self._shape is None:
+            inf = self.info()
+            self._shape = (inf["nbr"], inf["nbc"], inf["bs_r"], inf["bs_c"], inf["dtype"])
+        return self._shape
 
     def __del__(self):
         if getattr(self, "_destroy", False) and self.h and _lib is not None:
@@ -241,12 +272,23 @@ def bsr_mark_modified(A: Bsr):
     _check(_lib.bsr_mark_modified(A.h), "bsr_mark_modified")
 
 
+def _spmv_args(A: Bsr, x, y, nrhs, transpose):
+    nbr, nbc, br, bc, dt = A.shape_info()
+    if not 1 <= int(nrhs) <= 8:
+        raise ValueError("nrhs must be in 1..8")
+    nx, ny = (nbr * br, nbc * bc) if transpose else (nbc * bc, nbr * br)
+    _dev_tensor(y, ny * nrhs, _vec_dtypes(dt), "y")
+    _dev_tensor(x, nx * nrhs, (dtype_code(y),), "x")
+
+
 def bsr_spmv(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
+    _spmv_args(A, x, y, nrhs, False)
     _check(_lib.bsr_spmv(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs, _stream(stream)),
            "bsr_spmv")
 
 
 def bsr_spmv_t(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
+    _spmv_args(A, x, y, nrhs, True)
     _check(_lib.bsr_spmv_t(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs, _stream(stream)),
            "bsr_spmv_t")
 
@@ -278,8 +320,10 @@ def ptap_numeric(A: Bsr, P: Bsr, Cm: Bsr, stream=None):
 
 
 class CooPlan:
-    def __init__(self, h):
+    def __init__(self, h, n=None, block=None):
         self.h = h
+        self.n = n            # coordinates the plan was made from (value stream length)
+        self.block = block    # (bs_r, bs_c)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -300,10 +344,15 @@ def coo_plan_create(nbr, nbc, bs_r, bs_c, i: np.ndarray, j: np.ndarray, val_dtyp
     plan, A = _p(), _p()
     _check(_lib.coo_plan_create(nbr, nbc, bs_r, bs_c, len(i), i.ctypes.data_as(_p), j.ctypes.data_as(_p),
                                 val_dtype, C.byref(plan), C.byref(A)), "coo_plan_create")
-    return CooPlan(plan), Bsr(A)
+    return CooPlan(plan, len(i), (bs_r, bs_c)), Bsr(A)
 
 
 def coo_assemble_blocked(plan: CooPlan, vals, mode, A: Bsr, stream=None):
+    _, _, br, bc, dt = A.shape_info()
+    if plan.n is not None:
+        _dev_tensor(vals, plan.n * br * bc, (dt,), "vals")
+    if mode not in (INSERT, ADD):
+        raise ValueError("mode must be INSERT or ADD")
     _check(_lib.coo_assemble_blocked(plan.h, _ptr(vals), dtype_code(vals), mode, A.h, _stream(stream)),
            "coo_assemble_blocked")
 
@@ -609,7 +658,19 @@ def use_torch_allocator(enable=True):
     blkamg_set_allocator(alloc, free)
 
 
+def _fine_dofs(M: Amg) -> int:
+    n = getattr(M, "_fine_dofs", None)
+    if n is None:
+        A0, _ = M.level(0)
+        nbr, _, br, _, _ = A0.shape_info()
+        n = M._fine_dofs = nbr * br
+    return n
+
+
 def vcycle_apply(M: Amg, r, z, nrhs=1, stream=None):
+    n = _fine_dofs(M) * int(nrhs)
+    _dev_tensor(r, n, (F64,), "r")
+    _dev_tensor(z, n, (F64,), "z")
     _check(_lib.vcycle_apply(M.h, _ptr(r), _ptr(z), nrhs, _stream(stream)), "vcycle_apply")
 
 
@@ -617,6 +678,9 @@ def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, nrhs=1, stream=None):
     """Returns (status, iterations, relative residual); status OK or ENOCONV.  For one
     instance and nrhs = 1 the last two are scalars, otherwise int32 / float64 arrays
     [n_inst][nrhs]."""
+    nbr, _, br, _, _ = A.shape_info()
+    _dev_tensor(b, nbr * br * int(nrhs), (F64,), "b")
+    _dev_tensor(x, nbr * br * int(nrhs), (F64,), "x")
     k = M.num_instances()
     it = np.zeros(k * nrhs, dtype=np.int32)
     rr = np.zeros(k * nrhs, dtype=np.float64)

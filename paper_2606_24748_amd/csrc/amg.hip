@@ -734,7 +734,7 @@ std::vector<double> judge_level_bs(amg_s* M, int l, int k, hipStream_t s) {
     lanczos_scale_kernel<BS, double><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, jsc.p, step, wu.p, wy.p, u + n, y + n);
     HIP_CHECK(hipGetLastError());
   }
-  std::vector<LevelScalars> h = download(jsc.p, static_cast<size_t>(ns));
+  std::vector<LevelScalars> h = download(jsc.p, static_cast<size_t>(ns), s);
   std::vector<double> lam(static_cast<size_t>(ns));
   for (int t = 0; t < ns; ++t) {
     int m = std::min(k, (L.seg_off[t + 1] - L.seg_off[t]) * BS);  // no more steps than dofs
@@ -834,8 +834,8 @@ void mlp_refresh(amg_s* M, hipStream_t s) {
     refresh_level_scalars(M, l, M->pred_lam.p + M->sample_base[l], s);
     growth_level(M, l, s);
   }
-  std::vector<LevelScalars> sc = download(M->sc.p, static_cast<size_t>(nl) * M->n_inst);
-  std::vector<double> om = download(M->pred_omega.p, static_cast<size_t>(std::max(S, 0)));
+  std::vector<LevelScalars> sc = download(M->sc.p, static_cast<size_t>(nl) * M->n_inst, s);
+  std::vector<double> om = download(M->pred_omega.p, static_cast<size_t>(std::max(S, 0)), s);
   M->fallback.assign(static_cast<size_t>(nl), 0);
   M->growth.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
   M->omega.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
@@ -920,7 +920,7 @@ std::vector<int32_t> aggregate_level_device(Level& L, const std::vector<uint8_t>
   int32_t n_agg = 0;
   const int rc = sa_aggregate_device(A, dir.empty() ? nullptr : ddir.p, seed, dagg.p, &n_agg, nullptr, s);
   if (rc != BLKAMG_OK) fail(rc, std::string("sa_aggregate_device: ") + blkamg_last_error());
-  agg = download(dagg.p, static_cast<size_t>(A->nbr));
+  agg = download(dagg.p, static_cast<size_t>(A->nbr), s);
   return {n_agg};
 }
 
@@ -1423,7 +1423,7 @@ int pcg_batched(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol,
     HIP_CHECK(hipEventRecord(M->ev[1], M->gs));
     HIP_CHECK(hipStreamWaitEvent(s, M->ev[1], 0));
   }
-  std::vector<double> h = download(bs, static_cast<size_t>(B_FIELDS) * stride);
+  std::vector<double> h = download(bs, static_cast<size_t>(B_FIELDS) * stride, s);
   bool any_brk = false, any_noconv = false;
   for (int k = 0; k < nsys; ++k) {
     const double bb = h[B_BB * stride + k], rr = h[B_RR * stride + k], dn = h[B_DONE * stride + k];

@@ -147,10 +147,27 @@ inline void upload(DevBuf<T>& d, const std::vector<T>& h) {
   if (!h.empty()) HIP_CHECK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// Device -> host copy after all work queued on the device, whatever stream it was
+// queued on (a plain hipMemcpy on the null stream does not wait for non-blocking
+// streams).
 template <class T>
 inline std::vector<T> download(const T* d, size_t n) {
   std::vector<T> h(n);
-  if (n) HIP_CHECK(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+  if (n) {
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+  }
+  return h;
+}
+
+// Device -> host copy ordered after the work queued on stream s.
+template <class T>
+inline std::vector<T> download(const T* d, size_t n, hipStream_t s) {
+  std::vector<T> h(n);
+  if (n) {
+    HIP_CHECK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
   return h;
 }
 

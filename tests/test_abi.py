@@ -150,3 +150,70 @@ def test_new_wrappers_reject_bad_arguments_on_the_host():
                  "sa_aggregate_device")
     with pytest.raises(B.BlkAmgError):
         B._check(B._lib.fe_ebe_plan_create(None, 0, None, None, B.C.byref(B._p())), "fe_ebe_plan_create")
+
+
+def _stub_matrix(nbr, nbc, br, bc, dtype):
+    """A handle object with a known shape and no library matrix behind it: the
+    wrappers' host-side checks run before any library call."""
+    A = B.Bsr.__new__(B.Bsr)
+    A.h, A._keep, A._destroy, A._owner = None, (), False, None
+    A._shape = (nbr, nbc, br, bc, dtype)
+    return A
+
+
+def test_spmv_wrappers_reject_bad_vectors_on_the_host():
+    import torch
+    A = _stub_matrix(4, 5, 3, 6, B.F64)
+    good_x = torch.zeros(5 * 6, dtype=torch.float64)
+    with pytest.raises(ValueError, match="on the GPU"):
+        B.bsr_spmv(A, 1.0, good_x, 0.0, torch.zeros(12, dtype=torch.float64))
+    # no tensor is on a GPU here: replace the check by one without the device test to
+    # reach the dtype, length and contiguity rules
+    orig = B._dev_tensor
+
+    def no_device(t, numel, dtypes, name):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if B.dtype_code(t) not in dtypes:
+            raise ValueError(f"{name} has dtype {t.dtype}")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    B._dev_tensor = no_device
+    try:
+        with pytest.raises(ValueError, match="elements"):       # y too short
+            B._spmv_args(A, good_x, torch.zeros(11, dtype=torch.float64), 1, False)
+        with pytest.raises(ValueError, match="dtype"):          # F32 x with F64 y
+            B._spmv_args(A, good_x.float(), torch.zeros(12, dtype=torch.float64), 1, False)
+        with pytest.raises(ValueError, match="dtype"):          # F32 vectors, F64 matrix
+            B._spmv_args(A, good_x.float(), torch.zeros(12, dtype=torch.float32), 1, False)
+        with pytest.raises(ValueError, match="elements"):       # transpose swaps the lengths
+            B._spmv_args(A, good_x, torch.zeros(12, dtype=torch.float64), 1, True)
+        B._spmv_args(A, torch.zeros(12, dtype=torch.float64), good_x, 1, True)
+        with pytest.raises(ValueError, match="contiguous"):
+            B._spmv_args(A, torch.zeros(60, dtype=torch.float64)[::2], torch.zeros(12, dtype=torch.float64),
+                         1, False)
+        with pytest.raises(ValueError, match="nrhs"):
+            B._spmv_args(A, good_x, torch.zeros(12, dtype=torch.float64), 9, False)
+        B._spmv_args(A, torch.zeros(30 * 8, dtype=torch.float64), torch.zeros(12 * 8, dtype=torch.float64), 8,
+                     False)
+        Af = _stub_matrix(4, 5, 3, 6, B.BF16)   # BF16 matrices take F32 vectors
+        B._spmv_args(Af, good_x.float(), torch.zeros(12, dtype=torch.float32), 1, False)
+    finally:
+        B._dev_tensor = orig
+
+
+def test_assembly_and_solve_wrappers_reject_host_tensors():
+    import torch
+    A = _stub_matrix(4, 4, 3, 3, B.F64)
+    plan = B.CooPlan(None, n=10, block=(3, 3))
+    with pytest.raises(ValueError, match="on the GPU"):
+        B.coo_assemble_blocked(plan, torch.zeros(10, 3, 3, dtype=torch.float64), B.INSERT, A)
+    plan.h = None
+    M = B.Amg.__new__(B.Amg)
+    M.h, M._keep, M._fine_dofs = None, (), 12
+    with pytest.raises(ValueError, match="on the GPU"):
+        B.vcycle_apply(M, torch.zeros(12, dtype=torch.float64), torch.zeros(12, dtype=torch.float64))
+    with pytest.raises(ValueError, match="on the GPU"):
+        B.pcg_solve(A, M, torch.zeros(12, dtype=torch.float64), torch.zeros(12, dtype=torch.float64))
+    with pytest.raises(ValueError, match="device tensor"):
+        B.bsr_spmv(A, 1.0, torch.zeros(12, dtype=torch.float64), 0.0, None)

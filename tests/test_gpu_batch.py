@@ -270,3 +270,52 @@ def test_autotune_keeps_results(batch):
     B.bsr_spmv(HA, 1.0, X, 0.0, y1, nrhs=NR)
     assert rel2(y1.cpu().numpy(), y0.cpu().numpy()) <= 1e-14
     print(f"autotuned lane code {code}", flush=True)
+
+
+# Edge lengths spanning the batching workload's range 16..48: the largest instance has
+# four levels and the smallest three, so instances end on different levels at scale.
+WIDE = [16, 48, 31]
+WIDE_COLS = (0, 7)
+
+
+@pytest.fixture(scope="module")
+def wide():
+    print(f"wide batch sizes={WIDE} nrhs={NR}", flush=True)
+    bt = synth.make_batch(WIDE, nrhs=NR)
+    n = bt["n_nodes"]
+    A = S.coo_assemble(n, n, bt["i"], bt["j"], synth.batch_values(bt))
+    plan, HA = B.coo_plan_create(n, n, 3, 3, bt["i"], bt["j"])
+    B.coo_assemble_blocked(plan, dev(synth.batch_values(bt)), B.INSERT, HA)
+    H = OB.setup_batch(A, bt["row0"], bt["coords"], bt["dirichlet"])
+    torch.cuda.synchronize()
+    return dict(bt=bt, A=A, plan=plan, HA=HA, H=H)
+
+
+def test_wide_batch_hierarchy_vcycle_and_pcg(wide):
+    """Hierarchy per instance (aggregates, P, A_c, lambda_hat), the 8-column V-cycle and
+    the 8-column CG against the per-instance oracle on two of the columns."""
+    M = _setup(wide)
+    _check_levels(M, wide["H"])
+    bt, H, A = wide["bt"], wide["H"], wide["A"]
+    n_dof = bt["n_nodes"] * 3
+    R = np.random.default_rng(6).uniform(-1, 1, (n_dof, NR))
+    Z = torch.zeros(n_dof, NR, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, dev(R), Z, nrhs=NR)
+    Zh = Z.cpu().numpy()
+    b = bt["b"]
+    x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+    code, its, rel = B.pcg_solve(wide["HA"], M, dev(b), x, rtol=1e-8, nrhs=NR)
+    assert code == B.OK and np.all(rel <= 1e-8)
+    xs = x.cpu().numpy()
+    row0 = bt["row0"]
+    for t, h in enumerate(H):
+        a, c = row0[t] * 3, row0[t + 1] * 3
+        At = OB.extract_instance(A, int(row0[t]), int(row0[t + 1]))
+        for q in WIDE_COLS:
+            assert rel2(Zh[a:c, q], OS.vcycle(h, R[a:c, q])) <= 1e-11, (t, q)
+            _, it_o, _, ok = OS.pcg(At, b[a:c, q], lambda r: OS.vcycle(h, r), rtol=1e-8)
+            assert ok and abs(int(its[t, q]) - it_o) <= 1, (t, q, its[t, q], it_o)
+        for q in range(NR):
+            bq = b[a:c, q]
+            assert np.linalg.norm(bq - S.spmv(At, xs[a:c, q])) <= 2e-8 * np.linalg.norm(bq), (t, q)
+    print(f"wide batch pcg its={its.tolist()}", flush=True)

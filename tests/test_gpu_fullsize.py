@@ -133,3 +133,52 @@ def test_fullsize_hierarchy_galerkin_identity_and_pcg(big, hier, pdt):
     B.bsr_spmv(HA, -1.0, x, 1.0, r)
     assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 2e-8
     print(f"hier={hier} pcg its={it} relres={rel:.2e}", flush=True)
+
+
+def _column_rows(P: S.Bsr, cols):
+    """Block rows of P holding a block in each of the given columns."""
+    rows = np.repeat(np.arange(P.nbr), np.diff(P.rowptr))
+    return {int(a): rows[P.colidx == a].tolist() for a in cols}
+
+
+def test_fullsize_ptap_sampled_blocks_match_oracle(big):
+    """After a hot recompute of the FP64 hierarchy, sampled blocks of A_c on every level
+    against the oracle's block-by-block definition sum_{I,J} P_Ia^T A_IJ P_Jb, on the
+    GPU's own A and P of that level: random blocks plus every block of the longest
+    coarse rows (the most contributions per output) and of the first and last rows."""
+    m, HA = big["m"], big["HA"]
+    M = B.amg_setup(HA, m.coords, m.dirichlet)
+    lam2, mu2 = synth.lame(*synth.materials(m.n_elem, 1011))
+    B.coo_assemble_blocked(big["plan"], synth.coo_values_torch(m, lam2, mu2, "cuda"), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for l in range(3):
+        A = from_device_bsr(M.level(l)[0])
+        P = from_device_bsr(M.level(l)[1])
+        Ac = from_device_bsr(M.level(l + 1)[0])
+        rlen = np.diff(Ac.rowptr)
+        rows = np.concatenate([np.argsort(-rlen, kind="stable")[:3], [0, Ac.nbr - 1]])
+        picks = set(rng.integers(0, Ac.nnzb, 200).tolist())
+        for r in rows:
+            picks.update(range(int(Ac.rowptr[r]), int(Ac.rowptr[r + 1])))
+        picks = np.array(sorted(picks))
+        brow = np.searchsorted(Ac.rowptr, picks, side="right") - 1
+        cols = Ac.colidx[picks]
+        crow = _column_rows(P, np.unique(brow))
+        diag = {}
+        for a in np.unique(brow):
+            k = int(Ac.rowptr[a]) + int(np.nonzero(Ac.colidx[Ac.rowptr[a]:Ac.rowptr[a + 1]] == a)[0][0])
+            diag[int(a)] = np.linalg.norm(Ac.val[k])
+        worst, num, den = 0.0, 0.0, 0.0
+        for t, a, bcol in zip(picks, brow, cols):
+            want = S.ptap_block(A, P, int(a), int(bcol), crow)
+            d = np.linalg.norm(Ac.val[t] - want)
+            num, den = num + d * d, den + np.linalg.norm(want) ** 2
+            err = d / diag[int(a)]        # relative to the row's diagonal block (blocks can cancel)
+            worst = max(worst, err)
+            assert err <= 1e-12, (l, int(a), int(bcol), err)
+        frob = np.sqrt(num / den)
+        print(f"level {l + 1}: {len(picks)} sampled blocks, worst {worst:.2e}, Frobenius {frob:.2e}", flush=True)
+        assert frob <= 1e-12
+        del A, P, Ac
