@@ -462,9 +462,11 @@ def run_fe(args, B, torch, dev, stream):
 def run_learned(args, B, torch, dev, stream):
     """Deployment of the learned eigenbound on Q1 elasticity at learned_n^3 elements
     (material seed 21, redraw 1021, right-hand side seed 22): FP32 hierarchy with
-    Lanczos refresh vs FP32 hierarchy with the network refresh (growth test, Lanczos
-    fallback), plus the plain FP64 path; one step = assemble + recompute + refresh +
-    PCG to 1e-8.  lambda errors are taken against 50-step reorthogonalised Lanczos."""
+    Lanczos estimates vs FP32 hierarchy with the network, which supplies each level's
+    lambda_hat and prolongator-smoothing weight omega from the cold setup on (growth
+    test, Lanczos fallback), plus the plain FP64 path.  Each is timed as cold setup
+    (wall clock) and hot steps (assemble + recompute + refresh + PCG to 1e-8);
+    lambda errors are taken against 50-step reorthogonalised Lanczos."""
     import numpy as np
 
     import synth
@@ -484,13 +486,14 @@ def run_learned(args, B, torch, dev, stream):
         B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
         o = B.blkamg_opts_default()
         o.hier_dtype, o.p_dtype, o.eig_mode = hier, hier, eig
+        keep = B.opts_with_model(o, model) if eig == B.EIG_MLP else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
         t_setup = time.perf_counter() - t0
-        if eig == B.EIG_MLP:
-            B.amg_set_eig_model(M, model)
+        del keep
         x = torch.zeros_like(b)
+        code, its0, rel0 = B.pcg_solve(HA, M, b, x, rtol=1e-8, maxit=1000)  # solve on the setup's own values
         rec = []
         for s in range(args.warmup + args.steps):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -513,10 +516,15 @@ def run_learned(args, B, torch, dev, stream):
         med = {k: statistics.median(r[k] for r in rec) for k in ("coo_ms", "ptap_ms", "refresh_ms", "pcg_ms")}
         lam = M.lambdas().tolist()
         judge = B.amg_judge_lambdas(M, 50)[:, 0].tolist()
-        ent = {"setup_s": t_setup, "median_ms": med, "steps": rec, "lambda": lam, "lambda_judge": judge,
-               "lambda_rel_err": [a / j - 1.0 for a, j in zip(lam, judge)],
+        s_lam, s_om, s_learned = B.amg_setup_weights(M)
+        ent = {"setup_s": t_setup, "setup_pcg_its": its0, "median_ms": med, "steps": rec, "lambda": lam,
+               "lambda_judge": judge, "lambda_rel_err": [a / j - 1.0 for a, j in zip(lam, judge)],
+               "setup_lambda": s_lam[:, 0].tolist(), "setup_omega": s_om[:, 0].tolist(),
+               "setup_learned": s_learned.tolist(), "iterations": [r["its"] for r in rec],
                "refresh_plus_pcg_ms": med["refresh_ms"] + med["pcg_ms"],
+               "hot_step_ms": med["ptap_ms"] + med["refresh_ms"] + med["pcg_ms"],
                "ptap_plus_pcg_ms": med["ptap_ms"] + med["pcg_ms"]}
+        ent["setup_plus_hot_step_s"] = t_setup + ent["hot_step_ms"] * 1e-3
         if eig == B.EIG_MLP:
             fb, g, om = B.amg_eig_status(M)
             ent["fallback_levels"] = fb.tolist()
@@ -525,10 +533,12 @@ def run_learned(args, B, torch, dev, stream):
         res[name] = ent
         del M
         torch.cuda.synchronize()
-    res["mlp_vs_lanczos_refresh_speedup"] = (res["mixed-lanczos"]["median_ms"]["refresh_ms"] /
-                                             res["mixed-mlp"]["median_ms"]["refresh_ms"])
-    res["mixed_mlp_vs_fp64_solve_speedup"] = (res["fp64-lanczos"]["refresh_plus_pcg_ms"] /
-                                              res["mixed-mlp"]["refresh_plus_pcg_ms"])
+    lz, nn, fp = res["mixed-lanczos"], res["mixed-mlp"], res["fp64-lanczos"]
+    res["mlp_vs_lanczos_refresh_speedup"] = lz["median_ms"]["refresh_ms"] / nn["median_ms"]["refresh_ms"]
+    res["mlp_vs_lanczos_hot_step_speedup"] = lz["hot_step_ms"] / nn["hot_step_ms"]
+    res["mlp_vs_lanczos_setup_plus_hot_step_speedup"] = lz["setup_plus_hot_step_s"] / nn["setup_plus_hot_step_s"]
+    res["mlp_minus_lanczos_iterations"] = [a - c for a, c in zip(nn["iterations"], lz["iterations"])]
+    res["mixed_mlp_vs_fp64_solve_speedup"] = fp["refresh_plus_pcg_ms"] / nn["refresh_plus_pcg_ms"]
     return res
 
 
@@ -555,14 +565,16 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
     (assembly, Galerkin recompute, refresh, PCG) over warmup + steps passes."""
     tag = tag or var
     o = variant_opts(B, var)
+    keep = None
+    if var == "mixed-mlp":  # the network's lambda_hat and omega from the cold setup on
+        from paper_2606_24748_amd import train_eigmlp
+        keep = B.opts_with_model(o, train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL))
     B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M = B.amg_setup(HA, mesh.coords, mesh.dirichlet, o)
     t_setup = time.perf_counter() - t0
-    if var == "mixed-mlp":
-        from paper_2606_24748_amd import train_eigmlp
-        B.amg_set_eig_model(M, train_eigmlp.load_model(args.model or train_eigmlp.DEFAULT_MODEL))
+    del keep
     nl = M.num_levels()
     lev = []
     for l in range(nl):
@@ -742,7 +754,20 @@ def main(argv=None):
     t_plan = time.perf_counter() - t0
     a_inf = HA.info()
     log(f"coo plan: nnzb={a_inf['nnzb']} ({t_plan:.1f}s)")
-    del ii, jj
+    # the same plan built on the device from device coordinates (best of 3, each sync)
+    di, dj = torch.as_tensor(ii, device=dev), torch.as_tensor(jj, device=dev)
+    t_dplan = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dplan, dHA = B.coo_plan_create(mesh.n_nodes, mesh.n_nodes, 3, 3, di, dj)
+        t_dplan.append(time.perf_counter() - t0)
+        same = dHA.info()["nnzb"] == a_inf["nnzb"]
+        del dplan, dHA
+    plan_dev = {"device_s": min(t_dplan), "host_s": t_plan, "same_nnzb": bool(same), "entries": int(len(ii))}
+    log(f"coo plan on the device: {1e3 * min(t_dplan):.1f} ms (host {1e3 * t_plan:.0f} ms)")
+    del ii, jj, di, dj
+    torch.cuda.empty_cache()
 
     stream = torch.cuda.current_stream()
     if args.probe_only:
@@ -814,6 +839,7 @@ def main(argv=None):
                      "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
         "ptap_roofline": _ptap_roofline(RL, hr),
         "copy_GBs": copy["GBs"],
+        "coo_plan_ms": {"host": 1e3 * t_plan, "device": 1e3 * plan_dev["device_s"]},
         "cpu_baseline": cpu,
     }
     alt = {}
@@ -830,7 +856,7 @@ def main(argv=None):
         out["mixed_value"] = results["mixed"]["pcg_plus_ptap_s"]
         out["mixed_speedup_vs_fp64"] = value / results["mixed"]["pcg_plus_ptap_s"]
     detail = {"variants": results, "spmv_probe": probe, "copy": copy, "aggregation": aggregation,
-              "coo_plan_s": t_plan, **side}
+              "coo_plan_s": t_plan, "coo_plan": plan_dev, **side}
     line = json.dumps(detail)
     print("[bench] detail " + line, file=sys.stderr, flush=True)
     if args.detail_out:

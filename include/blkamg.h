@@ -183,15 +183,23 @@ int ptap_numeric(bsr_t A, bsr_t P, bsr_t C, void* stream);
  * Blocked COO assembly (paper §3.4 and §5)
  * ========================================================================== */
 
-/* Preallocation: from n block coordinates (h_i[k], h_j[k]) (host arrays; a
- * negative i or j marks an entry that is ignored) build the sorted unique block
- * pattern and the duplicate-summation plan, and create the matrix *A_out
- * (library-owned, values zero, type `val_dtype`).  Coordinates >= nbr / nbc are
- * EINVAL.  The index map is the stable order of the valid entries by
- * (row, column, position).  Sync.  Free with coo_plan_destroy and bsr_destroy. */
+/* Preallocation: from n block coordinates (i[k], j[k]) (a negative i or j marks an
+ * entry that is ignored) build the sorted unique block pattern and the
+ * duplicate-summation plan, and create the matrix *A_out (library-owned, values
+ * zero, type `val_dtype`).  Coordinates >= nbr / nbc are EINVAL.  The index map is
+ * the stable order of the valid entries by (row, column, position), the same bits
+ * whichever side builds it.
+ *   where = BLKAMG_HOST  : i, j are host arrays; the plan is built on the host
+ *                          (stream unused);
+ *   where = BLKAMG_DEVICE: i, j are device arrays; the plan is built on the device
+ *                          on `stream` (stable radix sort of 64-bit keys
+ *                          row * nbc + col), and no host copy of the pattern is made.
+ * Sync.  Free with coo_plan_destroy and bsr_destroy. */
+#define BLKAMG_HOST 0
+#define BLKAMG_DEVICE 1
 int coo_plan_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t n,
-                    const int32_t* h_i, const int32_t* h_j, int val_dtype,
-                    coo_plan_t* plan, bsr_t* A_out);
+                    const int32_t* i, const int32_t* j, int where, int val_dtype,
+                    coo_plan_t* plan, bsr_t* A_out, void* stream);
 int coo_plan_destroy(coo_plan_t plan);
 /* The plan's index map: d_perm int32[n_valid] (positions of valid entries in
  * sorted order) and d_seg int32[nnzb+1] (block t sums perm[seg[t]..seg[t+1])).
@@ -274,12 +282,23 @@ typedef struct {
                                compiled shape of each hierarchy SpMV (and of A0) for that
                                many right-hand sides and keep the fastest.  Default 0 */
   int32_t eig_mode;         /* BLKAMG_EIG_LANCZOS (default) or BLKAMG_EIG_MLP: refreshes
-                               take lambda_hat from the model set by amg_set_eig_model
-                               (the cold setup always uses Lanczos) */
+                               take lambda_hat from the model (eig_model below, or the
+                               one set by amg_set_eig_model); with eig_model set, the cold
+                               setup also takes each level's lambda_hat and its
+                               prolongator-smoothing weight omega from the network
+                               (P = (I - omega D^-1 A) P~, paper §2.2) */
   int32_t agg_mode;         /* BLKAMG_AGG_GREEDY (default): host aggregation in natural
                                order; BLKAMG_AGG_LUBY: sa_aggregate_device with agg_seed
                                on every level (one instance, strength_eps = 0) */
   uint64_t agg_seed;        /* priority seed of BLKAMG_AGG_LUBY, default 0x4D495332 */
+  int32_t growth_steps;     /* guard of the learned eigenbound: power steps of the
+                               smoother's error propagation from a fixed vector; a level
+                               whose last step grows the A-norm (or whose prediction is
+                               not positive and finite) falls back to Lanczos.  1..16,
+                               default 3 */
+  const float* eig_model;   /* host copy of a model (BLKAMG_MLP_MODEL floats) used from
+                               the cold setup on when eig_mode is BLKAMG_EIG_MLP (copied;
+                               NULL = none until amg_set_eig_model).  Default NULL */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -311,6 +330,20 @@ int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
  * Sync (one 4-byte read per round); allocates scratch. */
 int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg,
                         int32_t* n_agg, int32_t* n_rounds, void* stream);
+/* Tentative prolongator on the device (paper §2.2; the device-resident setup of §6):
+ * per aggregate, the near-null-space rows of its members in ascending node order,
+ * B_g = Q_g R_g by a thin Householder QR with diag(R_g) > 0; the members' rows of P~
+ * are the rows of Q_g and R_g is the coarse near-null space.
+ *   d_agg : device int32[nbr], aggregate id 0..n_agg-1 or -1 (row of P~ left zero);
+ *           every id must be used
+ *   d_B   : device double [nbr][bs][6], the near-null space (bs in 1..8)
+ *   d_Pt  : device double [nbr][bs][6] output (values of P~ row by row; its pattern
+ *           is one block per aggregated row, in column d_agg[i])
+ *   d_Bc  : device double [n_agg][6][6] output (R_g row-major)
+ * EINVAL for an aggregate with fewer than 6 rows, a rank-deficient one (|R_kk| <=
+ * 1e-10 max(1, max|B_g|)), or one with more than 682 rows.  Sync; allocates scratch. */
+int sa_tentative_device(int32_t nbr, int32_t bs, const int32_t* d_agg, int32_t n_agg, const double* d_B,
+                        double* d_Pt, double* d_Bc, void* stream);
 /* One smoothed-aggregation level on the host from the fine block pattern (paper §2.2,
  * §3.2): the greedy aggregation of sa_aggregate, the tentative prolongator P~ of the
  * six rigid-body modes built from h_coords ([n_nodes][3], bs = 3: per aggregate a thin
@@ -489,14 +522,21 @@ int amg_judge_lambdas(amg_t M, int32_t k, double* h_lam, void* stream);
  * feature mean[12], feature std[12], target mean[2], target std[2]; targets are
  * (log lambda_max, omega).  With eig_mode BLKAMG_EIG_MLP, amg_smoother_refresh
  * then takes lambda_hat = exp(prediction) per (level, instance), runs the smoother
- * growth test on every level (A-norm of one smoother application to a fixed
- * splitmix64 vector from f = 0 must not grow) and falls back to Lanczos on each
- * level where some instance fails it.  Sync (copies the model). */
+ * growth test on every level (A-norm of the last of opts.growth_steps smoother
+ * applications to a fixed splitmix64 vector, from f = 0, must not grow) and falls back
+ * to Lanczos on each level where some instance fails it.  Sync (copies the model). */
 int amg_set_eig_model(amg_t M, const float* h_model, int32_t n_floats);
 /* Outcome of the last MLP refresh: h_fallback[n_levels-1] (1 = level fell back to
  * Lanczos), h_growth and h_omega [n_levels-1][n_inst] (growth factor of the test
  * and predicted prolongator weight; 0 where not smoothed).  Any may be NULL. */
 int amg_eig_status(amg_t M, int32_t* h_fallback, double* h_growth, double* h_omega);
+/* What the cold setup used on each smoothed level (paper §2.2: P = (I - omega D^-1 A) P~):
+ * h_lambda and h_omega [n_levels-1][n_inst] (the lambda_hat the setup's smoother
+ * and the weight its prolongator smoothing used; 0 where not smoothed) and
+ * h_learned[n_levels-1] (1 = from the network, which passed the growth test; 0 =
+ * Lanczos with omega = omega_scale / lambda_hat).  Any may be NULL.  Hierarchies
+ * from caller operators report zeros. */
+int amg_setup_weights(amg_t M, double* h_lambda, double* h_omega, int32_t* h_learned);
 
 #ifdef __cplusplus
 }

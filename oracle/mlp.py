@@ -181,15 +181,21 @@ def judge_lambda(A: S.Bsr, Dinv: np.ndarray, k: int = 50, seed: int = 0x5EED) ->
 GROWTH_SEED = 0xC0FFEE
 
 
-def growth(A: S.Bsr, Dinv: np.ndarray, lam: float, opts: solve.Options, seed: int = GROWTH_SEED) -> float:
-    """A-norm growth of one application of the level's smoother error propagation,
-    sqrt(e1^T A e1 / e0^T A e0) with e0 from `start_vector` and e1 the smoother's
-    result for f = 0 from x0 = e0.  With the Chebyshev interval covering the spectrum
-    of D^-1 A the smoother contracts in the A-norm (value < 1); an interval whose upper
-    end is well below lambda_max amplifies the top of the spectrum (value > 1)."""
+def growth(A: S.Bsr, Dinv: np.ndarray, lam: float, opts: solve.Options, seed: int = GROWTH_SEED,
+           steps: int = 1) -> float:
+    """A-norm growth of the level's smoother error propagation S (the smoother's result
+    for f = 0) after `steps` applications: e_0 from `start_vector`, e_k = S e_(k-1), and
+    the value sqrt(e_k^T A e_k / e_(k-1)^T A e_(k-1)) of the last application.  With the
+    Chebyshev interval covering the spectrum of D^-1 A the smoother contracts in the
+    A-norm (value < 1); an interval whose upper end is well below lambda_max amplifies
+    the top of the spectrum (value > 1).  Repeated applications let the amplified modes
+    dominate, so the last ratio approaches the largest |p(lambda)| over the spectrum."""
     n = A.nbr * A.br
-    e0 = start_vector(n, seed)
-    e1 = solve.chebyshev(A, Dinv, lam, np.zeros(n), e0, opts.cheb_degree, opts.cheb_lo, opts.cheb_hi)
-    a0 = e0 @ S.spmv(A, e0)
-    a1 = e1 @ S.spmv(A, e1)
-    return float(np.sqrt(max(a1, 0.0) / a0))
+    e = start_vector(n, seed)
+    a_prev = e @ S.spmv(A, e)
+    a_cur = a_prev
+    for _ in range(steps):
+        a_prev = a_cur
+        e = solve.chebyshev(A, Dinv, lam, np.zeros(n), e, opts.cheb_degree, opts.cheb_lo, opts.cheb_hi)
+        a_cur = e @ S.spmv(A, e)
+    return float(np.sqrt(max(a_cur, 0.0) / a_prev))

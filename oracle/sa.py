@@ -246,15 +246,17 @@ def lanczos_lambda_max(A: S.Bsr, Dinv: np.ndarray, k: int = 10, seed: int = LANC
 
 
 def smooth_prolongator(A: S.Bsr, Pt: S.Bsr, Dinv: np.ndarray, lam: float,
-                       omega_scale: float = 4.0 / 3.0) -> S.Bsr:
+                       omega_scale: float = 4.0 / 3.0, omega: float | None = None) -> S.Bsr:
     """Damped-Jacobi prolongator smoothing (paper §2.2): P = (I - omega D^-1 A) P~ with
     D the block diagonal (reading of "the diagonal" for the blocked method) and
-    omega = 4 / (3 lambda_hat) (reading: the classical SA weight).  The pattern of P is
-    the structural pattern of A P~ (no dropping)."""
+    omega = 4 / (3 lambda_hat) (reading: the classical SA weight), or the weight given
+    in `omega` (a weight from another estimate of lambda_max, such as a learned one).
+    The pattern of P is the structural pattern of A P~ (no dropping)."""
     rp, ci = S.structural_product(A.rowptr, A.colidx, A.nbr, A.nbc, Pt.rowptr, Pt.colidx, Pt.nbc)
     AP = S.reblock(S.to_scalar_csr(A) @ S.to_scalar_csr(Pt), A.nbr, Pt.nbc, A.br, Pt.bc, rp, ci)
     PtOn = S.reblock(S.to_scalar_csr(Pt), A.nbr, Pt.nbc, A.br, Pt.bc, rp, ci)
-    omega = omega_scale / lam
+    if omega is None:
+        omega = omega_scale / lam
     rows = AP.block_rows()
     val = PtOn.val - omega * np.einsum("tij,tjk->tik", Dinv[rows], AP.val)
     return AP.with_values(val)

@@ -140,10 +140,14 @@ def pcg(A: S.Bsr, b: np.ndarray, precond, rtol: float = 1e-8, maxit: int = 1000)
     return x, it, np.linalg.norm(r) / bn, False
 
 
-def setup(A0: S.Bsr, coords: np.ndarray, dirichlet: np.ndarray, opts: Options | None = None) -> Hierarchy:
+def setup(A0: S.Bsr, coords: np.ndarray, dirichlet: np.ndarray, opts: Options | None = None,
+          level_params=None) -> Hierarchy:
     """Cold setup (paper §3.1, §3.2): per level aggregate, build P~ from the near-null
     space, estimate lambda_max, smooth P, form A_c = P^T A P; stop when the level has at
-    most `coarse_eq_limit` dofs or `max_levels` is reached; factor the coarsest level."""
+    most `coarse_eq_limit` dofs or `max_levels` is reached; factor the coarsest level.
+    `level_params[l] = (lambda_hat, omega)` replaces level l's Lanczos estimate and its
+    prolongator-smoothing weight (for a hierarchy whose estimates came from elsewhere,
+    such as the learned eigenbound); None keeps the method's own."""
     o = opts or Options()
     H = Hierarchy(opts=o)
     A = A0
@@ -160,8 +164,12 @@ def setup(A0: S.Bsr, coords: np.ndarray, dirichlet: np.ndarray, opts: Options | 
             break
         Pt, Bc = sa.tentative_prolongator(agg, n_agg, B)
         Dinv = S.block_diag_inverse(A)
-        lam, _, _ = sa.lanczos_lambda_max(A, Dinv, o.lanczos_steps, o.lanczos_seed + lev)
-        P = sa.smooth_prolongator(A, Pt, Dinv, lam, o.omega_scale)
+        if level_params is not None and level_params[lev] is not None:
+            lam, omega = level_params[lev]
+        else:
+            lam, _, _ = sa.lanczos_lambda_max(A, Dinv, o.lanczos_steps, o.lanczos_seed + lev)
+            omega = None
+        P = sa.smooth_prolongator(A, Pt, Dinv, lam, o.omega_scale, omega)
         H.levels.append(Level(A=A, P=P, Dinv=Dinv, lam=lam, agg=agg, n_agg=n_agg))
         A = S.ptap(A, P)
         B = Bc

@@ -60,6 +60,8 @@ class Opts(C.Structure):
         ("eig_mode", C.c_int32),
         ("agg_mode", C.c_int32),
         ("agg_seed", C.c_uint64),
+        ("growth_steps", C.c_int32),
+        ("eig_model", C.c_void_p),
     ]
 
 
@@ -78,7 +80,8 @@ _SIG = {
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
     "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
     "ptap_numeric": (C.c_int, [_p, _p, _p, _p]),
-    "coo_plan_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, C.c_int, C.POINTER(_p), C.POINTER(_p)]),
+    "coo_plan_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, C.c_int, C.c_int, C.POINTER(_p),
+                                  C.POINTER(_p), _p]),
     "coo_plan_destroy": (C.c_int, [_p]),
     "coo_plan_map": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_i64), C.POINTER(_i64)]),
     "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
@@ -90,6 +93,7 @@ _SIG = {
     "fe_q1_assemble_ebe": (C.c_int, [_p, _p, _p, _p, _p, _p, C.c_int, _p]),
     "blkamg_opts_default": (None, [C.POINTER(Opts)]),
     "sa_aggregate": (C.c_int, [_i32, _p, _p, _p, _p, _pi32]),
+    "sa_tentative_device": (C.c_int, [_i32, _i32, _p, _i32, _p, _p, _p, _p]),
     "sa_setup_host": (C.c_int, [_i32, _p, _p, _p, _p, C.POINTER(Opts), C.POINTER(_p)]),
     "sa_result_info": (C.c_int, [_p, _pi32, C.POINTER(_i64), C.POINTER(_i64)]),
     "sa_result_arrays": (C.c_int, [_p] + [C.POINTER(_p)] * 7),
@@ -116,6 +120,7 @@ _SIG = {
     "amg_judge_lambdas": (C.c_int, [_p, _i32, _p, _p]),
     "amg_set_eig_model": (C.c_int, [_p, _p, _i32]),
     "amg_eig_status": (C.c_int, [_p, _p, _p, _p]),
+    "amg_setup_weights": (C.c_int, [_p, _p, _p, _p]),
     "pcg_solve": (C.c_int, [_p, _p, _p, _p, _f64, _i32, _i32, _pi32, C.POINTER(_f64), _p]),
 }
 
@@ -337,14 +342,36 @@ class CooPlan:
         return _from_ptr(perm.value, nv.value, torch.int32), _from_ptr(seg.value, nb.value + 1, torch.int32)
 
 
-def coo_plan_create(nbr, nbc, bs_r, bs_c, i: np.ndarray, j: np.ndarray, val_dtype=F64):
-    """Host coordinate arrays (int32 numpy); returns (plan, A) with A library-owned."""
-    i = np.ascontiguousarray(i, dtype=np.int32)
-    j = np.ascontiguousarray(j, dtype=np.int32)
+HOST, DEVICE = 0, 1
+
+
+def coo_plan_create(nbr, nbc, bs_r, bs_c, i, j, val_dtype=F64, where=None, stream=None):
+    """Coordinates as host int32 arrays (numpy; plan built on the host) or as int32 device
+    tensors (plan built on the device); `where` defaults to the side the arrays live on.
+    Returns (plan, A) with A library-owned."""
+    on_dev = hasattr(i, "is_cuda") and i.is_cuda
+    if where is None:
+        where = DEVICE if on_dev else HOST
+    if where == DEVICE:
+        import torch
+        for t, name in ((i, "i"), (j, "j")):
+            if not (hasattr(t, "is_cuda") and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous int32 device tensor for a device plan")
+        if i.numel() != j.numel():
+            raise ValueError("i and j differ in length")
+        n = i.numel()
+        pi, pj = _ptr(i), _ptr(j)
+    else:
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        if len(i) != len(j):
+            raise ValueError("i and j differ in length")
+        n = len(i)
+        pi, pj = i.ctypes.data_as(_p), j.ctypes.data_as(_p)
     plan, A = _p(), _p()
-    _check(_lib.coo_plan_create(nbr, nbc, bs_r, bs_c, len(i), i.ctypes.data_as(_p), j.ctypes.data_as(_p),
-                                val_dtype, C.byref(plan), C.byref(A)), "coo_plan_create")
-    return CooPlan(plan, len(i), (bs_r, bs_c)), Bsr(A)
+    _check(_lib.coo_plan_create(nbr, nbc, bs_r, bs_c, n, pi, pj, int(where), val_dtype, C.byref(plan), C.byref(A),
+                                _stream(stream) if where == DEVICE else None), "coo_plan_create")
+    return CooPlan(plan, n, (bs_r, bs_c)), Bsr(A)
 
 
 def coo_assemble_blocked(plan: CooPlan, vals, mode, A: Bsr, stream=None):
@@ -372,6 +399,24 @@ def sa_aggregate_device(A: Bsr, dirichlet=None, seed=LUBY_SEED, stream=None):
     _check(_lib.sa_aggregate_device(A.h, _ptr(d), seed, _ptr(agg), C.byref(na), C.byref(nr), _stream(stream)),
            "sa_aggregate_device")
     return agg, na.value, nr.value
+
+
+def sa_tentative_device(agg, n_agg, B_null, stream=None):
+    """P~ values [nbr, bs, 6] and the coarse near-null space [n_agg, 6, 6] from device
+    tensors agg (int32 [nbr]) and B_null (float64 [nbr, bs, 6])."""
+    import torch
+    nbr = agg.numel()
+    if B_null.dim() != 3 or B_null.shape[0] != nbr or B_null.shape[2] != 6:
+        raise ValueError("B_null must be [nbr, bs, 6]")
+    bs = B_null.shape[1]
+    if agg.dtype != torch.int32 or not agg.is_cuda or not agg.is_contiguous():
+        raise ValueError("agg must be a contiguous int32 device tensor")
+    _dev_tensor(B_null, nbr * bs * 6, (F64,), "B_null")
+    pt = torch.empty(nbr, bs, 6, dtype=torch.float64, device="cuda")
+    bc = torch.empty(max(n_agg, 0), 6, 6, dtype=torch.float64, device="cuda")
+    _check(_lib.sa_tentative_device(nbr, bs, _ptr(agg), int(n_agg), _ptr(B_null), _ptr(pt), _ptr(bc),
+                                    _stream(stream)), "sa_tentative_device")
+    return pt, bc
 
 
 def _fe_inputs(elem_nodes, coords, lam, mu, check_nodes=True):
@@ -755,3 +800,28 @@ def amg_eig_status(M: Amg):
     _check(_lib.amg_eig_status(M.h, fb.ctypes.data_as(_p), g.ctypes.data_as(_p), om.ctypes.data_as(_p)),
            "amg_eig_status")
     return fb, g, om
+
+
+def amg_setup_weights(M: Amg):
+    """What the cold setup used per smoothed level: (lambda[n_levels-1][n_inst],
+    omega[n_levels-1][n_inst], learned[n_levels-1]) with learned = 1 where the network
+    supplied them."""
+    nl = max(M.num_levels() - 1, 0)
+    k = M.num_instances()
+    lam = np.zeros((nl, k))
+    om = np.zeros((nl, k))
+    le = np.zeros(nl, dtype=np.int32)
+    _check(_lib.amg_setup_weights(M.h, lam.ctypes.data_as(_p), om.ctypes.data_as(_p), le.ctypes.data_as(_p)),
+           "amg_setup_weights")
+    return lam, om, le
+
+
+def opts_with_model(opts: Opts, model: np.ndarray):
+    """Point opts.eig_model at a host float32 copy of `model` (BLKAMG_MLP_MODEL floats).
+    Returns the array, which must stay alive until the setup call has returned (the
+    library copies it)."""
+    arr = np.ascontiguousarray(model, dtype=np.float32)
+    if arr.size != MLP_MODEL:
+        raise ValueError(f"a model has {MLP_MODEL} floats, got {arr.size}")
+    opts.eig_model = arr.ctypes.data
+    return arr

@@ -106,6 +106,10 @@ struct amg_s {
   std::vector<int32_t> fallback;       // per level: 1 if the last refresh fell back to Lanczos
   std::vector<double> growth;          // [level][inst] A-norm growth of the smoother test
   std::vector<double> omega;           // [level][inst] predicted prolongator weight
+  // cold setup: lambda_hat and prolongator weight per [level][inst], and per level
+  // whether the network supplied them (1) or Lanczos (0)
+  std::vector<double> setup_lam, setup_omega;
+  std::vector<int32_t> setup_learned;
   bool user_ops = false;               // operators supplied by the caller (amg_hierarchy_create)
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -753,8 +757,11 @@ std::vector<double> judge_level(amg_s* M, int l, int k, hipStream_t s) {
 }
 
 // A-norm growth test of the smoother of level l with its current Chebyshev
-// coefficients: e0 from splitmix64 (seed kGrowthSeed), e1 = smoother result for
-// f = 0 from x0 = e0; sc[l][seg].tmp[1] = e0.Ae0, tmp[2] = e1.Ae1.
+// coefficients, as K = growth_steps power steps of the smoother's error propagation S
+// (the smoother's result for f = 0): e_0 from splitmix64 (seed kGrowthSeed),
+// e_k = S e_(k-1); sc[l][seg].tmp[1] = e_(K-1).A e_(K-1), tmp[2] = e_K.A e_K, so the
+// growth is the ratio of the last application, which repeated applications push
+// towards the largest |p(lambda)| over the spectrum.
 constexpr uint64_t kGrowthSeed = 0xC0FFEE;
 
 template <int BS, class TV>
@@ -779,17 +786,26 @@ void growth_level_bs(amg_s* M, int l, hipStream_t s) {
   lanczos_start_kernel<BS, TV, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, kGrowthSeed, val, L.diag_idx.p, e0, scratch);
   HIP_CHECK(hipGetLastError());
   const int G = lanes_for(A, 1);
-  launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
-  seg_reduce<1>(M, L.lgrid, e0, w, OpStoreTmp{sc, 1}, s);
-  {
-    EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, L.d_row_seg.p, 0};
-    smooth<M_INITX, 1, TV>(A, e0, e, s);
-  }
-  for (int t = 1; t < M->o.cheb_degree; ++t) {
-    const bool last = (t == M->o.cheb_degree - 1);
-    EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, x, x, dinv, sc, L.d_row_seg.p, t - 1};
-    smooth<M_STEP, 1, TV>(A, d, e, s);
-    std::swap(d, d2);
+  const int K = std::max(1, M->o.growth_steps);
+  for (int step = 0; step < K; ++step) {
+    if (step > 0) HIP_CHECK(hipMemcpyAsync(e0, x, n * sizeof(TV), hipMemcpyDeviceToDevice, s));
+    if (step == K - 1) {
+      launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
+      seg_reduce<1>(M, L.lgrid, e0, w, OpStoreTmp{sc, 1}, s);
+    }
+    {
+      EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, L.d_row_seg.p, 0};
+      smooth<M_INITX, 1, TV>(A, e0, e, s);
+    }
+    TV* dd = d;
+    TV* dd2 = d2;
+    for (int t = 1; t < M->o.cheb_degree; ++t) {
+      const bool last = (t == M->o.cheb_degree - 1);
+      EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, dd, last ? nullptr : dd2, x, x, dinv, sc, L.d_row_seg.p,
+                                  t - 1};
+      smooth<M_STEP, 1, TV>(A, dd, e, s);
+      std::swap(dd, dd2);
+    }
   }
   launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, x, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
   seg_reduce<1>(M, L.lgrid, x, w, OpStoreTmp{sc, 2}, s);
@@ -806,29 +822,46 @@ void growth_level(amg_s* M, int l, hipStream_t s) {
 // forward -> lambda, omega; then the Chebyshev coefficients from them, the growth
 // test on every level, and Lanczos on every level where some segment's smoother
 // grows the A-norm.  Sync.
+// Inference buffers for S samples.
+void ensure_mlp_buffers(amg_s* M, int S) {
+  if (M->feat.n >= static_cast<size_t>(std::max(S, 1)) * 12) return;
+  HIP_CHECK(hipDeviceSynchronize());
+  const size_t ns = static_cast<size_t>(std::max(S, 1));
+  M->feat.alloc(ns * 12);
+  M->fx.alloc(ns * 12);
+  M->fh1.alloc(ns * kMlpHid);
+  M->fh2.alloc(ns * kMlpHid);
+  M->fy.alloc(ns * kMlpOut);
+  M->pred_lam.alloc(ns);
+  M->pred_omega.alloc(ns);
+}
+
+// features (already in M->feat[0..S)) -> standardise -> forward -> pred_lam, pred_omega
+void mlp_predict(amg_s* M, int S, hipStream_t s) {
+  if (S <= 0) return;
+  const float* stats = M->model.p + kMlpParams;
+  feature_normalize_kernel<<<(S * 12 + 255) / 256, 256, 0, s>>>(S, M->feat.p, stats, M->fx.p);
+  HIP_CHECK(hipGetLastError());
+  mlp_forward_dev(M->model.p, M->fx.p, S, M->fh1.p, M->fh2.p, M->fy.p, s);
+  predict_finish_kernel<<<(S + 255) / 256, 256, 0, s>>>(S, M->fy.p, stats + 24, M->pred_lam.p, M->pred_omega.p);
+  HIP_CHECK(hipGetLastError());
+}
+
+// A level's smoother from the network fails the guard when some segment's smoother
+// grows the A-norm or the predicted lambda_hat is not a positive finite number.
+bool growth_fails(const LevelScalars& q, double* g_out) {
+  const double g = q.tmp[1] > 0.0 ? std::sqrt(std::max(q.tmp[2], 0.0) / q.tmp[1]) : 0.0;
+  if (g_out) *g_out = g;
+  return !(g <= 1.0) || !(q.lam > 0.0) || !std::isfinite(q.lam);
+}
+
 void mlp_refresh(amg_s* M, hipStream_t s) {
   BLK_REQUIRE(M->model.p != nullptr, BLKAMG_ESTATE, "eig_mode is MLP but no model was set (amg_set_eig_model)");
   const int nl = static_cast<int>(M->lv.size());
   const int S = M->n_samples;
-  if (M->feat.n < static_cast<size_t>(S) * 12 + 1) {
-    const size_t ns = static_cast<size_t>(std::max(S, 1));
-    M->feat.alloc(ns * 12);
-    M->fx.alloc(ns * 12);
-    M->fh1.alloc(ns * kMlpHid);
-    M->fh2.alloc(ns * kMlpHid);
-    M->fy.alloc(ns * kMlpOut);
-    M->pred_lam.alloc(ns);
-    M->pred_omega.alloc(ns);
-  }
+  ensure_mlp_buffers(M, S);
   all_features(M, M->feat.p, s);
-  if (S > 0) {
-    const float* stats = M->model.p + kMlpParams;
-    feature_normalize_kernel<<<(S * 12 + 255) / 256, 256, 0, s>>>(S, M->feat.p, stats, M->fx.p);
-    HIP_CHECK(hipGetLastError());
-    mlp_forward_dev(M->model.p, M->fx.p, S, M->fh1.p, M->fh2.p, M->fy.p, s);
-    predict_finish_kernel<<<(S + 255) / 256, 256, 0, s>>>(S, M->fy.p, stats + 24, M->pred_lam.p, M->pred_omega.p);
-    HIP_CHECK(hipGetLastError());
-  }
+  mlp_predict(M, S, s);
   for (int l = 0; l < nl; ++l) {
     if (M->lv[l]->n_act == 0) continue;
     refresh_level_scalars(M, l, M->pred_lam.p + M->sample_base[l], s);
@@ -843,17 +876,59 @@ void mlp_refresh(amg_s* M, hipStream_t s) {
     const Level& L = *M->lv[l];
     bool bad = false;
     for (int t = 0; t < L.n_act; ++t) {
-      const LevelScalars& q = sc[static_cast<size_t>(l) * M->n_inst + t];
-      const double g = q.tmp[1] > 0.0 ? std::sqrt(std::max(q.tmp[2], 0.0) / q.tmp[1]) : 0.0;
+      double g = 0.0;
+      bad = growth_fails(sc[static_cast<size_t>(l) * M->n_inst + t], &g) || bad;
       M->growth[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = g;
       M->omega[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = om[M->sample_base[l] + t];
-      bad = bad || !(g <= 1.0) || !(q.lam > 0.0) || !std::isfinite(q.lam);
     }
     if (bad) {
       M->fallback[l] = 1;
       refresh_level_scalars(M, l, nullptr, s);
     }
   }
+}
+
+// Cold setup of level l's smoother scalars and prolongator weights (per smoothed
+// segment, into omega_seg): with a model and eig_mode MLP, the network's lambda_hat
+// (Chebyshev bounds) and omega (prolongator smoothing), kept when every segment's
+// smoother passes the growth test; otherwise, or without a model, Lanczos and
+// omega = omega_scale / lambda_hat.  Records both in M->setup_*.  Sync.
+void setup_level_scalars(amg_s* M, int l, std::vector<double>& omega_seg, hipStream_t s) {
+  Level& L = *M->lv[l];
+  const int na = L.n_act;
+  omega_seg.assign(static_cast<size_t>(na), 0.0);
+  const size_t nrec = static_cast<size_t>(l + 1) * M->n_inst;
+  if (M->setup_lam.size() < nrec) {
+    M->setup_lam.resize(nrec, 0.0);
+    M->setup_omega.resize(nrec, 0.0);
+  }
+  if (M->setup_learned.size() < static_cast<size_t>(l + 1)) M->setup_learned.resize(static_cast<size_t>(l + 1), 0);
+  M->setup_learned[l] = 0;
+  if (na == 0) return;
+  LevelScalars* scl = M->sc.p + static_cast<size_t>(l) * M->n_inst;
+  bool learned = false;
+  std::vector<double> om;
+  if (M->o.eig_mode == BLKAMG_EIG_MLP && M->model.p) {
+    ensure_mlp_buffers(M, na);
+    ensure_vectors(M, 1);
+    level_features(M, l, M->feat.p, s);
+    mlp_predict(M, na, s);
+    refresh_level_scalars(M, l, M->pred_lam.p, s);
+    growth_level(M, l, s);
+    std::vector<LevelScalars> q = download(scl, static_cast<size_t>(na), s);
+    om = download(M->pred_omega.p, static_cast<size_t>(na), s);
+    learned = true;
+    for (int t = 0; t < na; ++t)
+      learned = learned && !growth_fails(q[t], nullptr) && om[t] > 0.0 && std::isfinite(om[t]);
+  }
+  if (!learned) refresh_level_scalars(M, l, nullptr, s);
+  std::vector<LevelScalars> q = download(scl, static_cast<size_t>(na), s);
+  for (int t = 0; t < na; ++t) {
+    omega_seg[t] = learned ? om[t] : M->o.omega_scale / q[t].lam;
+    M->setup_lam[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = q[t].lam;
+    M->setup_omega[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = omega_seg[t];
+  }
+  M->setup_learned[l] = learned ? 1 : 0;
 }
 
 void galerkin_recompute(amg_s* M, hipStream_t s) {
@@ -964,6 +1039,18 @@ void check_opts(const blkamg_opts& o) {
               "autotune_nrhs must be 0, 1 or 8");
   BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
   BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || o.agg_mode == BLKAMG_AGG_LUBY, BLKAMG_EINVAL, "bad agg_mode");
+  BLK_REQUIRE(o.growth_steps >= 1 && o.growth_steps <= 16, BLKAMG_EINVAL, "growth_steps must be in 1..16");
+}
+
+// Validate and copy a model to the device (the caller's array is not kept).
+void set_model(amg_s* M, const float* h_model) {
+  for (int j = 0; j < 12; ++j)
+    BLK_REQUIRE(h_model[kMlpParams + 12 + j] > 0.f, BLKAMG_EINVAL, "feature std must be positive");
+  BLK_REQUIRE(h_model[kMlpParams + 26] > 0.f && h_model[kMlpParams + 27] > 0.f, BLKAMG_EINVAL,
+              "target std must be positive");
+  HIP_CHECK(hipDeviceSynchronize());
+  std::vector<float> h(h_model, h_model + kMlpModel);
+  upload(M->model, h);
 }
 
 // The parts of a hierarchy that do not depend on how its levels were made.
@@ -1035,6 +1122,8 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
   if (n_inst > 1) check_block_diagonal(A0, row0);
 
   auto M = new_amg(o, A0, n_inst, row0);
+  M->o.eig_model = nullptr;  // the caller's array is copied, never kept
+  if (o.eig_model) set_model(M.get(), o.eig_model);
 
   // ---- cold setup in F64 ----
   const int nc_bs = 6;
@@ -1058,7 +1147,15 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     L0->n_act = n_act;
     M->lv.push_back(std::move(L0));
   }
-  std::vector<double> B = rigid_body_modes(A0->nbr, h_coords);
+  // near-null space of the current level on the device: the rigid-body modes of the
+  // fine nodes, then each level's coarse near-null space
+  DevBuf<double> dB(static_cast<size_t>(A0->nbr) * 3 * nc_bs);
+  {
+    DevBuf<double> dcoords;
+    upload(dcoords, std::vector<double>(h_coords, h_coords + static_cast<size_t>(A0->nbr) * 3));
+    rigid_body_modes_device(A0->nbr, dcoords.p, dB.p, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
   std::vector<uint8_t> dir;
   if (h_dirichlet) dir.assign(h_dirichlet, h_dirichlet + A0->nbr);
   for (;;) {
@@ -1101,13 +1198,25 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     for (int t = 0; t < L.n_act; ++t)
       for (int32_t i = L.seg_off[t]; i < L.seg_off[t + 1]; ++i)
         if (agg[i] >= 0) agg[i] += base[t];
-    std::vector<double> Pt, Bc;
-    tentative_host(L.act_rows, L.bs, nc_bs, agg, n_agg, B, Pt, Bc);
+    // tentative prolongator: per-aggregate QR on the device (the host QR only for an
+    // aggregate too large for the device kernel)
+    DevBuf<int32_t> dagg;
+    upload(dagg, agg);
+    DevBuf<double> dpt(static_cast<size_t>(L.act_rows) * L.bs * nc_bs);
+    DevBuf<double> dBc(static_cast<size_t>(n_agg) * nc_bs * nc_bs);
+    if (!tentative_device(L.act_rows, L.bs, dagg.p, n_agg, dB.p, dpt.p, dBc.p, s)) {
+      std::vector<double> Bh = download(dB.p, static_cast<size_t>(L.act_rows) * L.bs * nc_bs, s);
+      std::vector<double> Pt, Bc;
+      tentative_host(L.act_rows, L.bs, nc_bs, agg, n_agg, Bh, Pt, Bc);
+      upload(dpt, Pt);
+      upload(dBc, Bc);
+    }
     L.agg = std::move(agg);
     L.n_agg = n_agg;
     compute_dinv(M.get(), L, s);
     check_flags(M.get(), s);
-    refresh_level_scalars(M.get(), l, nullptr, s);
+    std::vector<double> omega_seg;
+    setup_level_scalars(M.get(), l, omega_seg, s);
     // smoothed prolongator: pattern of A P~ on the host, values on the device
     bsr_s* A = L.A_act.get();
     std::vector<int32_t> ptrp(static_cast<size_t>(A->nbr) + 1, 0), ptci;
@@ -1119,24 +1228,21 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     structural_product_host(A->nbr, A->h_rowptr, A->h_colidx, n_agg, ptrp, ptci, prp, pci);
     L.P = make_owned(A->nbr, n_agg, A->br, nc_bs, BLKAMG_F64, std::move(prp), std::move(pci));
     {
-      DevBuf<int32_t> dagg;
-      upload(dagg, L.agg);
-      DevBuf<double> dpt;
-      upload(dpt, Pt);
+      DevBuf<double> dom;
+      upload(dom, omega_seg);
       const int64_t nnz = L.P->nnzb;
-      const LevelScalars* scl = M->sc.p + static_cast<size_t>(l) * n_inst;
       if (nnz > 0) {
         const int grid = static_cast<int>((nnz + 255) / 256);
 #define BLK_SMOOTHP(BS)                                                                                          \
   smooth_p_kernel<BS, 6><<<grid, 256, 0, s>>>(A->nbr, A->rowptr, A->colidx, static_cast<const double*>(A->val),  \
                                               dagg.p, dpt.p, reinterpret_cast<const double*>(L.dinv.p),          \
-                                              L.d_act_off.p, L.n_act, scl, o.omega_scale, L.P->rowptr,           \
+                                              L.d_act_off.p, L.n_act, dom.p, L.P->rowptr,                       \
                                               L.P->colidx, static_cast<double*>(L.P->val))
         if (A->br == 3) BLK_SMOOTHP(3); else BLK_SMOOTHP(6);
 #undef BLK_SMOOTHP
         HIP_CHECK(hipGetLastError());
       }
-      HIP_CHECK(hipStreamSynchronize(s));  // dagg / dpt are freed at scope exit
+      HIP_CHECK(hipStreamSynchronize(s));  // dom (and dagg / dpt below) are freed at scope exit
     }
     bsr_t Cm = nullptr;
     int rc = ptap_symbolic_ex(A, L.P.get(), BLKAMG_PTAP_SYMMETRIC, &Cm, stream);
@@ -1145,7 +1251,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     next->A = Cm;
     rc = ptap_numeric(A, L.P.get(), Cm, stream);
     if (rc != BLKAMG_OK) fail(rc, std::string("ptap_numeric: ") + blkamg_last_error());
-    B = std::move(Bc);
+    dB = std::move(dBc);
     dir.clear();
     M->lv.push_back(std::move(next));
   }
@@ -1461,6 +1567,8 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->eig_mode = BLKAMG_EIG_LANCZOS;
   o->agg_mode = BLKAMG_AGG_GREEDY;
   o->agg_seed = 0x4D495332ull;
+  o->growth_steps = 3;
+  o->eig_model = nullptr;
 }
 
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream,
@@ -1588,6 +1696,8 @@ int amg_hierarchy_create(int32_t n_levels, const bsr_t* A, const bsr_t* P, const
   const std::vector<int32_t> row0{0, A[0]->nbr};
   auto M = new_amg(o, A[0], 1, row0);
   M->user_ops = true;
+  M->o.eig_model = nullptr;  // the caller's array is copied, never kept
+  if (o.eig_model) set_model(M.get(), o.eig_model);
   for (int l = 0; l < n_levels; ++l) {
     auto L = std::make_unique<Level>();
     L->A = A[l];
@@ -1680,13 +1790,22 @@ int amg_set_eig_model(amg_t M, const float* h_model, int32_t n_floats) {
   BLK_API_BEGIN
   BLK_REQUIRE(M != nullptr && h_model != nullptr, BLKAMG_EINVAL, "NULL argument");
   BLK_REQUIRE(n_floats == kMlpModel, BLKAMG_EINVAL, "a model has BLKAMG_MLP_MODEL floats");
-  for (int j = 0; j < 12; ++j)
-    BLK_REQUIRE(h_model[kMlpParams + 12 + j] > 0.f, BLKAMG_EINVAL, "feature std must be positive");
-  BLK_REQUIRE(h_model[kMlpParams + 26] > 0.f && h_model[kMlpParams + 27] > 0.f, BLKAMG_EINVAL,
-              "target std must be positive");
-  HIP_CHECK(hipDeviceSynchronize());
-  std::vector<float> h(h_model, h_model + kMlpModel);
-  upload(M->model, h);
+  set_model(M, h_model);
+  BLK_API_END
+}
+
+int amg_setup_weights(amg_t M, double* h_lambda, double* h_omega, int32_t* h_learned) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  const size_t nl = M->lv.size();
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    if (h_learned) h_learned[l] = l < M->setup_learned.size() ? M->setup_learned[l] : 0;
+    for (int t = 0; t < M->n_inst; ++t) {
+      const size_t k = l * M->n_inst + t;
+      if (h_lambda) h_lambda[k] = k < M->setup_lam.size() ? M->setup_lam[k] : 0.0;
+      if (h_omega) h_omega[k] = k < M->setup_omega.size() ? M->setup_omega[k] : 0.0;
+    }
+  }
   BLK_API_END
 }
 

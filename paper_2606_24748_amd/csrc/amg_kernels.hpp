@@ -483,15 +483,16 @@ struct EpiSmooth {
 };
 
 // ---------------------------------------------------------------------------
-// Prolongator smoothing (cold setup, paper §2.2), omega = omega_scale / lambda_seg:
+// Prolongator smoothing (cold setup, paper §2.2) with the weight omega of the row's
+// segment (omega_scale / lambda_hat, or a learned weight):
 //   P_ib = [agg(i) == b] P~_i - omega Dinv_i sum_{j in A_i, agg(j) == b} A_ij P~_j
 // ---------------------------------------------------------------------------
 template <int BS, int NC>
 __global__ void smooth_p_kernel(int nbr, const int32_t* __restrict__ a_rp, const int32_t* __restrict__ a_ci,
                                 const double* __restrict__ a_v, const int32_t* __restrict__ agg,
                                 const double* __restrict__ pt, const double* __restrict__ dinv,
-                                const int32_t* __restrict__ off, int nseg, const LevelScalars* __restrict__ sc,
-                                double omega_scale, const int32_t* __restrict__ p_rp, const int32_t* __restrict__ p_ci,
+                                const int32_t* __restrict__ off, int nseg, const double* __restrict__ omega_seg,
+                                const int32_t* __restrict__ p_rp, const int32_t* __restrict__ p_ci,
                                 double* __restrict__ p_v) {
   const int64_t gidx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t nnz = p_rp[nbr];
@@ -516,7 +517,7 @@ __global__ void smooth_p_kernel(int nbr, const int32_t* __restrict__ a_rp, const
         for (int c = 0; c < NC; ++c) acc[r * NC + c] += a * pb[m * NC + c];
       }
   }
-  const double omega = omega_scale / sc[seg_of(off, nseg, i)].lam;
+  const double omega = omega_seg[seg_of(off, nseg, i)];
   const double* D = dinv + static_cast<size_t>(i) * BS * BS;
   double* o = p_v + static_cast<size_t>(gidx) * BS * NC;
   for (int r = 0; r < BS; ++r)

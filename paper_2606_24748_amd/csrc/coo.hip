@@ -2,7 +2,10 @@
 // duplicate-summation plan is built, and every numeric assembly is one device
 // kernel that sums contiguous bs_r*bs_c value runs into the block matrix.
 #include <algorithm>
+#include <string>
 #include <thread>
+
+#include <hipcub/hipcub.hpp>
 
 #include "internal.hpp"
 
@@ -87,6 +90,148 @@ void launch_sum(const coo_plan_s* p, const T* vals, T* out, int add, hipStream_t
   HIP_CHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Plan creation on the device: the same index map as the host plan.  Valid entries
+// are compacted in stream order, their 64-bit keys row * nbc + col are sorted by a
+// stable radix sort (equal keys keep ascending stream position), and the runs of
+// equal keys give the segments and the unique sorted pattern.
+// ---------------------------------------------------------------------------
+__global__ void coo_valid_kernel(int64_t n, const int32_t* __restrict__ ci, const int32_t* __restrict__ cj,
+                                 int32_t nbr, int32_t nbc, int32_t* __restrict__ flag,
+                                 unsigned long long* __restrict__ bad) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (k >= n) return;
+  const int32_t i = ci[k], j = cj[k];
+  const bool valid = i >= 0 && j >= 0;
+  flag[k] = valid ? 1 : 0;
+  if (valid && (i >= nbr || j >= nbc)) atomicMin(bad, static_cast<unsigned long long>(k));
+}
+
+__global__ void coo_compact_kernel(int64_t n, const int32_t* __restrict__ ci, const int32_t* __restrict__ cj,
+                                   int32_t nbc, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                   uint64_t* __restrict__ key, int32_t* __restrict__ src) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (k >= n || !flag[k]) return;
+  const int32_t p = pos[k];
+  key[p] = static_cast<uint64_t>(ci[k]) * static_cast<uint64_t>(nbc) + static_cast<uint64_t>(cj[k]);
+  src[p] = static_cast<int32_t>(k);
+}
+
+__global__ void coo_head_kernel(int64_t nv, const uint64_t* __restrict__ key, int32_t* __restrict__ head) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t >= nv) return;
+  head[t] = (t == 0 || key[t] != key[t - 1]) ? 1 : 0;
+}
+
+// Unique block u starts at sorted position t (head[t] = 1, u = uid[t]): its segment
+// start, its column, and the row pointers of the rows up to its own.
+__global__ void coo_pattern_kernel(int64_t nv, const uint64_t* __restrict__ key, const int32_t* __restrict__ head,
+                                   const int32_t* __restrict__ uid, int32_t nbc, int32_t nbr, int32_t nnzb,
+                                   int32_t* __restrict__ seg, int32_t* __restrict__ colidx,
+                                   int32_t* __restrict__ rowptr) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t >= nv || !head[t]) return;
+  const int32_t u = uid[t];
+  const uint64_t k = key[t];
+  const int32_t row = static_cast<int32_t>(k / static_cast<uint64_t>(nbc));
+  seg[u] = static_cast<int32_t>(t);
+  colidx[u] = static_cast<int32_t>(k - static_cast<uint64_t>(row) * static_cast<uint64_t>(nbc));
+  const int32_t prev = t == 0 ? -1 : static_cast<int32_t>(key[t - 1] / static_cast<uint64_t>(nbc));
+  for (int32_t r = prev + 1; r <= row; ++r) rowptr[r] = u;  // rows prev+1..row start at block u
+  if (u == nnzb - 1) {
+    for (int32_t r = row + 1; r <= nbr; ++r) rowptr[r] = nnzb;
+    seg[nnzb] = static_cast<int32_t>(nv);
+  }
+}
+
+int bits_of(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+template <class T>
+void exclusive_sum(const T* in, T* out, int64_t n, hipStream_t s) {
+  size_t bytes = 0;
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, static_cast<int>(n), s));
+  DevBuf<char> tmp(std::max<size_t>(bytes, 1));
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, in, out, static_cast<int>(n), s));
+}
+
+int32_t read_last_sum(const int32_t* excl, const int32_t* flags, int64_t n, hipStream_t s) {
+  int32_t a = 0, b = 0;
+  HIP_CHECK(hipMemcpyAsync(&a, excl + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&b, flags + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return a + b;
+}
+
+// Device plan of n coordinates d_i, d_j (device int32): perm, seg, rowptr, colidx on
+// the device; *n_valid, *nnzb.  Sync (a few scalar reads).
+void coo_plan_device(int32_t nbr, int32_t nbc, int64_t n, const int32_t* d_i, const int32_t* d_j, hipStream_t s,
+                     DevBuf<int32_t>& perm, DevBuf<int32_t>& seg, DevBuf<int32_t>& rowptr, DevBuf<int32_t>& colidx,
+                     int64_t& n_valid, int64_t& nnzb) {
+  n_valid = 0;
+  nnzb = 0;
+  rowptr.alloc(static_cast<size_t>(nbr) + 1);
+  HIP_CHECK(hipMemsetAsync(rowptr.p, 0, rowptr.bytes(), s));
+  if (n == 0) {
+    seg.alloc(1);
+    HIP_CHECK(hipMemsetAsync(seg.p, 0, sizeof(int32_t), s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return;
+  }
+  const int grid = static_cast<int>((n + 255) / 256);
+  DevBuf<int32_t> flag(static_cast<size_t>(n)), pos(static_cast<size_t>(n));
+  DevBuf<unsigned long long> bad(1);
+  const unsigned long long none = ~0ull;
+  HIP_CHECK(hipMemcpyAsync(bad.p, &none, sizeof(none), hipMemcpyHostToDevice, s));
+  coo_valid_kernel<<<grid, 256, 0, s>>>(n, d_i, d_j, nbr, nbc, flag.p, bad.p);
+  HIP_CHECK(hipGetLastError());
+  unsigned long long hb = 0;
+  HIP_CHECK(hipMemcpyAsync(&hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  BLK_REQUIRE(hb == none, BLKAMG_EINVAL, "COO coordinate out of range at entry " + std::to_string(hb));
+  exclusive_sum(flag.p, pos.p, n, s);
+  const int32_t nv = read_last_sum(pos.p, flag.p, n, s);
+  n_valid = nv;
+  if (nv == 0) {
+    perm.release();
+    seg.alloc(1);
+    HIP_CHECK(hipMemsetAsync(seg.p, 0, sizeof(int32_t), s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return;
+  }
+  DevBuf<uint64_t> key(static_cast<size_t>(nv)), key2(static_cast<size_t>(nv));
+  DevBuf<int32_t> src(static_cast<size_t>(nv));
+  perm.alloc(static_cast<size_t>(nv));
+  coo_compact_kernel<<<grid, 256, 0, s>>>(n, d_i, d_j, nbc, flag.p, pos.p, key.p, src.p);
+  HIP_CHECK(hipGetLastError());
+  flag.release();
+  pos.release();
+  const int end_bit = std::max(1, bits_of(static_cast<uint64_t>(std::max(nbr, 1)) * static_cast<uint64_t>(std::max(nbc, 1))));
+  size_t sort_bytes = 0;
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key.p, key2.p, src.p, perm.p, nv, 0, end_bit, s));
+  {
+    DevBuf<char> tmp(std::max<size_t>(sort_bytes, 1));
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp.p, sort_bytes, key.p, key2.p, src.p, perm.p, nv, 0, end_bit, s));
+  }
+  key.release();
+  src.release();
+  DevBuf<int32_t> head(static_cast<size_t>(nv)), uid(static_cast<size_t>(nv));
+  const int vgrid_ = static_cast<int>((static_cast<int64_t>(nv) + 255) / 256);
+  coo_head_kernel<<<vgrid_, 256, 0, s>>>(nv, key2.p, head.p);
+  HIP_CHECK(hipGetLastError());
+  exclusive_sum(head.p, uid.p, nv, s);
+  const int32_t nu = read_last_sum(uid.p, head.p, nv, s);
+  nnzb = nu;
+  seg.alloc(static_cast<size_t>(nu) + 1);
+  colidx.alloc(static_cast<size_t>(nu));
+  coo_pattern_kernel<<<vgrid_, 256, 0, s>>>(nv, key2.p, head.p, uid.p, nbc, nbr, nu, seg.p, colidx.p, rowptr.p);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
 }  // namespace
 }  // namespace blk
 
@@ -95,7 +240,8 @@ using namespace blk;
 extern "C" {
 
 int coo_plan_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t n, const int32_t* h_i,
-                    const int32_t* h_j, int val_dtype, coo_plan_t* plan, bsr_t* A_out) {
+                    const int32_t* h_j, int where, int val_dtype, coo_plan_t* plan, bsr_t* A_out, void* stream) {
+  // h_i / h_j are device pointers when where == BLKAMG_DEVICE
   BLK_API_BEGIN
   BLK_REQUIRE(plan != nullptr && A_out != nullptr, BLKAMG_EINVAL, "output pointer is NULL");
   *plan = nullptr;
@@ -105,6 +251,42 @@ int coo_plan_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_
   BLK_REQUIRE(n == 0 || (h_i != nullptr && h_j != nullptr), BLKAMG_EINVAL, "coordinate array is NULL");
   BLK_REQUIRE(n <= INT32_MAX, BLKAMG_EINVAL, "stream longer than the int32 index range");
   BLK_REQUIRE(val_dtype == BLKAMG_F64 || val_dtype == BLKAMG_F32, BLKAMG_EINVAL, "COO values must be F64 or F32");
+  BLK_REQUIRE(where == BLKAMG_HOST || where == BLKAMG_DEVICE, BLKAMG_EINVAL, "where must be HOST or DEVICE");
+  if (where == BLKAMG_DEVICE) {
+    hipStream_t s = as_stream(stream);
+    auto P = std::make_unique<coo_plan_s>();
+    auto A = std::make_unique<bsr_s>();
+    DevBuf<int32_t> rp, ci;
+    int64_t nv = 0, nu = 0;
+    coo_plan_device(nbr, nbc, n, h_i, h_j, s, P->perm, P->seg, rp, ci, nv, nu);
+    BLK_REQUIRE(nu <= INT32_MAX, BLKAMG_EINVAL, "too many blocks");
+    P->nbr = nbr;
+    P->nbc = nbc;
+    P->br = bs_r;
+    P->bc = bs_c;
+    P->n = n;
+    P->n_valid = nv;
+    P->nnzb = nu;
+    A->nbr = nbr;
+    A->nbc = nbc;
+    A->br = bs_r;
+    A->bc = bs_c;
+    A->dtype = val_dtype;
+    A->nnzb = nu;
+    A->own_rowptr = std::move(rp);
+    A->own_colidx = std::move(ci);
+    A->own_val.alloc(A->val_bytes());
+    if (A->own_val.p) HIP_CHECK(hipMemsetAsync(A->own_val.p, 0, A->val_bytes(), s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    A->rowptr = A->own_rowptr.p;
+    A->colidx = A->own_colidx.p;
+    A->val = A->own_val.p;
+    P->rowptr = A->rowptr;
+    P->colidx = A->colidx;
+    *plan = P.release();
+    *A_out = A.release();
+    return BLKAMG_OK;
+  }
 
   // 1. count valid entries per block row (and check ranges)
   std::vector<int64_t> cnt(static_cast<size_t>(nbr) + 1, 0);

@@ -67,5 +67,10 @@ void structural_product_host(int32_t nra, const std::vector<int32_t>& rpa, const
                              std::vector<int32_t>& rpc, std::vector<int32_t>& cic);
 // Cast a value array between dtypes on the device.
 void cast_values(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
+// Tentative prolongator rows and coarse near-null space on the device (per-aggregate
+// Householder QR); false if an aggregate is too large for it (nothing computed).
+void rigid_body_modes_device(int32_t n, const double* d_coords, double* d_B, hipStream_t s);
+bool tentative_device(int32_t nbr, int32_t bs, const int32_t* d_agg, int32_t n_agg, const double* d_B, double* d_Pt,
+                      double* d_Bc, hipStream_t s);
 
 }  // namespace blk

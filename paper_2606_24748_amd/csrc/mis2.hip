@@ -17,6 +17,7 @@
 // three apart, so that root is unique) and the remaining vertices join the
 // neighbouring aggregate holding most of their neighbours, ties to the smallest id.
 #include <algorithm>
+#include <string>
 
 #include <hipcub/hipcub.hpp>
 
@@ -250,45 +251,47 @@ __global__ void mis_phase2_kernel(int32_t n, const int32_t* __restrict__ rp, con
   else agg[r.i] = best ? static_cast<int32_t>(0xFFFFFFFFull - (best & 0xFFFFFFFFull)) : -1;
 }
 
-}  // namespace
-}  // namespace blk
+// Byte layout of the scratch one aggregation needs (256-byte aligned pieces).
+struct MisScratch {
+  size_t off[9];
+  size_t total;
+  size_t scan_bytes;
+};
 
-using namespace blk;
+inline size_t up256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
-extern "C" {
-
-int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg, int32_t* n_agg,
-                        int32_t* n_rounds, void* stream) {
-  BLK_API_BEGIN
-  BLK_REQUIRE(A != nullptr && n_agg != nullptr, BLKAMG_EINVAL, "NULL argument");
-  BLK_REQUIRE(A->nbr == A->nbc, BLKAMG_EINVAL, "A must be square");
-  BLK_REQUIRE(A->nbr == 0 || d_agg != nullptr, BLKAMG_EINVAL, "d_agg is NULL");
-  const int32_t n = A->nbr;
-  *n_agg = 0;
-  if (n_rounds) *n_rounds = 0;
-  if (n == 0) return BLKAMG_OK;
-  hipStream_t s = as_stream(stream);
-  // one scratch allocation, carved into the arrays below (256-byte aligned pieces)
+MisScratch mis_scratch_layout(int32_t n, hipStream_t s) {
+  MisScratch L{};
   const size_t nn = static_cast<size_t>(n);
-  size_t scan_bytes = 0;
-  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<int32_t*>(nullptr),
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, L.scan_bytes, static_cast<int32_t*>(nullptr),
                                              static_cast<int32_t*>(nullptr), n, s));
-  auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
-  const size_t sizes[] = {nn * 8, nn * 8, nn, nn, nn * 4, nn * 4, nn * 4, 4, std::max<size_t>(scan_bytes, 1)};
-  size_t total = 0;
-  for (size_t b : sizes) total += up(b);
-  DevBuf<char> scratch(total);
-  char* cur = scratch.p;
-  auto take = [&](size_t b) { char* p = cur; cur += up(b); return p; };
-  auto* key = reinterpret_cast<uint64_t*>(take(sizes[0]));
-  auto* m1 = reinterpret_cast<uint64_t*>(take(sizes[1]));
-  auto* state = reinterpret_cast<uint8_t*>(take(sizes[2]));
-  auto* near = reinterpret_cast<uint8_t*>(take(sizes[3]));
-  auto* flag = reinterpret_cast<int32_t*>(take(sizes[4]));
-  auto* root_id = reinterpret_cast<int32_t*>(take(sizes[5]));
-  auto* agg1 = reinterpret_cast<int32_t*>(take(sizes[6]));
-  auto* counter = reinterpret_cast<int32_t*>(take(sizes[7]));
-  void* scan_tmp = take(sizes[8]);
+  // key, m1, state, near, flag, root_id, agg1, counter, scan temporary
+  const size_t sizes[] = {nn * 8, nn * 8, nn, nn, nn * 4, nn * 4, nn * 4, 4, std::max<size_t>(L.scan_bytes, 1)};
+  size_t cur = 0;
+  for (int k = 0; k < 9; ++k) {
+    L.off[k] = cur;
+    cur += up256(sizes[k]);
+  }
+  L.total = cur;
+  return L;
+}
+
+// The aggregation itself on caller-provided scratch of the layout above.  Every
+// scratch array is written before it is read (the counter by mis_zero_kernel), so its
+// previous contents do not matter.
+void mis_aggregate(const bsr_s* A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg, int32_t* n_agg,
+                   int32_t* n_rounds, char* base, const MisScratch& L, hipStream_t s) {
+  const int32_t n = A->nbr;
+  auto* key = reinterpret_cast<uint64_t*>(base + L.off[0]);
+  auto* m1 = reinterpret_cast<uint64_t*>(base + L.off[1]);
+  auto* state = reinterpret_cast<uint8_t*>(base + L.off[2]);
+  auto* near = reinterpret_cast<uint8_t*>(base + L.off[3]);
+  auto* flag = reinterpret_cast<int32_t*>(base + L.off[4]);
+  auto* root_id = reinterpret_cast<int32_t*>(base + L.off[5]);
+  auto* agg1 = reinterpret_cast<int32_t*>(base + L.off[6]);
+  auto* counter = reinterpret_cast<int32_t*>(base + L.off[7]);
+  void* scan_tmp = base + L.off[8];
+  size_t scan_bytes = L.scan_bytes;
   const int grid = (n + 255) / 256;
   const int64_t ggrid64 = (static_cast<int64_t>(n) * kG + 255) / 256;
   BLK_REQUIRE(ggrid64 <= INT32_MAX, BLKAMG_EINVAL, "too many vertices");
@@ -323,6 +326,28 @@ int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int3
   HIP_CHECK(hipStreamSynchronize(s));
   *n_agg = last_id + last_flag;
   if (n_rounds) *n_rounds = rounds;
+}
+
+}  // namespace
+}  // namespace blk
+
+using namespace blk;
+
+extern "C" {
+
+int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg, int32_t* n_agg,
+                        int32_t* n_rounds, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(A != nullptr && n_agg != nullptr, BLKAMG_EINVAL, "NULL argument");
+  BLK_REQUIRE(A->nbr == A->nbc, BLKAMG_EINVAL, "A must be square");
+  BLK_REQUIRE(A->nbr == 0 || d_agg != nullptr, BLKAMG_EINVAL, "d_agg is NULL");
+  *n_agg = 0;
+  if (n_rounds) *n_rounds = 0;
+  if (A->nbr == 0) return BLKAMG_OK;
+  hipStream_t s = as_stream(stream);
+  const MisScratch L = mis_scratch_layout(A->nbr, s);
+  DevBuf<char> buf(L.total);  // one scratch allocation, carved into the arrays
+  mis_aggregate(A, d_dirichlet, seed, d_agg, n_agg, n_rounds, buf.p, L, s);
   BLK_API_END
 }
 

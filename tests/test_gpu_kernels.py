@@ -111,6 +111,40 @@ def test_coo_plan_bit_exact_and_values():
         B.coo_plan_create(nbr, nbc, 3, 6, np.array([nbr], np.int32), np.array([0], np.int32))
 
 
+@pytest.mark.parametrize("nbr,nbc,n,seed", [(257, 131, 20000, 4), (3000, 3000, 150000, 5), (1, 1, 50, 6)])
+def test_coo_device_plan_bit_exact(nbr, nbc, n, seed):
+    """The plan built on the device from device coordinates: the same index map, segments
+    and pattern as the oracle's stable order by (row, column, position), bit for bit, and
+    the same assembled values."""
+    i, j, v = synth.random_coo_stream(nbr, nbc, 3, 3, n, seed=seed, neg_frac=0.1, dup_pool=max(n // 7, 1))
+    print(f"device coo plan nbr={nbr} nbc={nbc} n={n}", flush=True)
+    plan, H = B.coo_plan_create(nbr, nbc, 3, 3, dev(i), dev(j))
+    rp, ci, perm, seg = S.coo_plan(nbr, nbc, i, j)
+    dperm, dseg = plan.index_map()
+    assert np.array_equal(dperm.cpu().numpy(), perm)
+    assert np.array_equal(dseg.cpu().numpy(), seg)
+    got_rp, got_ci, _ = H.arrays()
+    assert np.array_equal(got_rp.cpu().numpy(), rp) and np.array_equal(got_ci.cpu().numpy(), ci)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, H)
+    assert np.array_equal(from_device_bsr(H).val, S.coo_assemble(nbr, nbc, i, j, v).val)
+
+
+def test_coo_device_plan_edge_cases():
+    # empty stream, all entries ignored, one entry, out-of-range coordinate
+    z = torch.zeros(0, dtype=torch.int32, device="cuda")
+    plan, H = B.coo_plan_create(5, 5, 3, 3, z, z)
+    assert H.info()["nnzb"] == 0 and plan.index_map()[1].cpu().tolist() == [0]
+    neg = dev(np.array([-1, 2, -3], np.int32))
+    plan, H = B.coo_plan_create(5, 5, 3, 3, neg, dev(np.array([1, -1, -1], np.int32)))
+    assert H.info()["nnzb"] == 0 and H.arrays()[0].cpu().tolist() == [0] * 6
+    plan, H = B.coo_plan_create(5, 4, 2, 2, dev(np.array([3], np.int32)), dev(np.array([2], np.int32)))
+    rp, ci, _ = H.arrays()
+    assert rp.cpu().tolist() == [0, 0, 0, 0, 1, 1] and ci.cpu().tolist() == [2]
+    with pytest.raises(B.BlkAmgError) as e:
+        B.coo_plan_create(5, 5, 3, 3, dev(np.array([0, 5], np.int32)), dev(np.array([0, 0], np.int32)))
+    assert e.value.code == B.EINVAL and "entry 1" in str(e.value)
+
+
 def test_coo_elasticity_stream_tiny_and_empty():
     m, i, j, v, A = q1_problem(8)
     plan, H = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)

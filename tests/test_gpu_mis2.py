@@ -101,3 +101,38 @@ def test_device_aggregation_degenerate_graphs():
         assert (n_agg, rounds) == (n_want, r_want)
         assert np.array_equal(agg.cpu().numpy(), want)
     assert n_agg == 0 and rounds == 0
+
+
+@pytest.mark.parametrize("n,luby", [(6, False), (12, False), (12, True)])
+def test_device_tentative_prolongator_matches_oracle(n, luby):
+    """The device QR per aggregate against oracle.sa.tentative_prolongator: P~ values
+    and the coarse near-null space within 1e-12, and P~ reproduces the rigid-body
+    modes exactly on aggregated rows (P~ B_c = B)."""
+    from oracle import sa as OSA
+    m = synth.make_mesh(n)
+    i, j = synth.coo_indices(m)
+    A = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 7))))
+    nbrs = OSA.strength_graph(A, m.dirichlet)
+    if luby:
+        agg, n_agg, _ = OSA.aggregate_luby(nbrs, m.dirichlet, OSA.LUBY_SEED)
+    else:
+        agg, n_agg = OSA.aggregate(nbrs, m.dirichlet)
+    Bn = OSA.rigid_body_modes(m.coords)
+    Pt_o, Bc_o = OSA.tentative_prolongator(agg, n_agg, Bn)
+    pt, bc = B.sa_tentative_device(torch.as_tensor(np.asarray(agg, dtype=np.int32)).cuda(), n_agg,
+                                   torch.as_tensor(Bn).cuda())
+    pt, bc = pt.cpu().numpy(), bc.cpu().numpy()
+    rows = np.nonzero(np.asarray(agg) >= 0)[0]
+    assert rel2(pt[rows], Pt_o.val) <= 1e-12
+    assert not np.any(pt[np.asarray(agg) < 0])
+    assert rel2(bc, Bc_o) <= 1e-12
+    recon = np.einsum("nij,njk->nik", pt[rows], bc[np.asarray(agg)[rows]])
+    assert np.abs(recon - Bn[rows]).max() <= 1e-12 * np.abs(Bn).max()
+
+
+def test_device_tentative_prolongator_rejects_small_aggregates():
+    agg = torch.tensor([0, 0, 1, 1, 1], dtype=torch.int32, device="cuda")  # aggregate 0: 2 nodes x bs 2 = 4 rows < 6
+    Bn = torch.rand(5, 2, 6, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BlkAmgError) as e:
+        B.sa_tentative_device(agg, 2, Bn)
+    assert e.value.code == B.EINVAL

@@ -15,7 +15,7 @@ from oracle import mlp as ML  # noqa: E402
 from oracle import solve as OS  # noqa: E402
 from oracle import sparse as S  # noqa: E402
 from paper_2606_24748_amd import blkamg as B  # noqa: E402
-from tests.gpu_util import dev, rel2  # noqa: E402
+from tests.gpu_util import dev, from_device_bsr, rel2  # noqa: E402
 
 
 def f32(a):
@@ -181,7 +181,7 @@ def test_mlp_refresh_uses_prediction_and_passes_growth_test():
     H = OS.setup(A, m.coords, m.dirichlet)
     for l in range(H.n_levels - 1):
         L = H.levels[l]
-        want = ML.growth(L.A, L.Dinv, float(M.lambdas()[l]), OS.Options())
+        want = ML.growth(L.A, L.Dinv, float(M.lambdas()[l]), OS.Options(), steps=B.blkamg_opts_default().growth_steps)
         assert abs(g[l, 0] - want) <= 1e-9 * want
     b = synth.rhs(m, 2)
     x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
@@ -198,7 +198,7 @@ def test_mlp_refresh_falls_back_when_bound_is_too_low():
     # the injected value 0.3 lambda_true of level 0 is far too low for every level
     low = 0.3 * lam_true[0]
     for l in range(H.n_levels - 1):
-        assert ML.growth(H.levels[l].A, H.levels[l].Dinv, low, OS.Options()) > 1.0 or low >= lam_true[l]
+        assert ML.growth(H.levels[l].A, H.levels[l].Dinv, low, OS.Options(), steps=3) > 1.0 or low >= lam_true[l]
     B.amg_set_eig_model(M, _const_model(low))
     B.amg_smoother_refresh(M)
     fb, g, _ = B.amg_eig_status(M)
@@ -220,3 +220,91 @@ def test_model_validation_and_missing_model():
     B.amg_smoother_refresh(M)  # no model yet: Lanczos
     fb, _, _ = B.amg_eig_status(M)
     assert not fb.any()
+
+
+def _learned_setup(n, seed, model):
+    """FP64 hierarchy whose cold setup takes lambda_hat and omega from `model`."""
+    m = synth.make_mesh(n)
+    i, j = synth.coo_indices(m)
+    v = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, seed)))
+    A = S.coo_assemble(m.n_nodes, m.n_nodes, i, j, v)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    o = B.blkamg_opts_default()
+    o.eig_mode = B.EIG_MLP
+    keep = B.opts_with_model(o, model)
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    del keep
+    return m, A, HA, M
+
+
+def _compare_setup_with_oracle(m, A, M, lam, om):
+    """The oracle's cold setup given the library's (lambda_hat, omega) per level: same
+    aggregates and patterns bit for bit, P and A_c within 1e-12."""
+    H = OS.setup(A, m.coords, m.dirichlet, level_params=[(float(lam[l, 0]), float(om[l, 0]))
+                                                          for l in range(M.num_levels() - 1)])
+    assert H.n_levels == M.num_levels()
+    for l in range(H.n_levels - 1):
+        L = H.levels[l]
+        assert np.array_equal(M.aggregates(l), L.agg)
+        P = from_device_bsr(M.level(l)[1])
+        assert np.array_equal(P.colidx, L.P.colidx) and rel2(P.val, L.P.val) <= 1e-12, l
+        Ac = from_device_bsr(M.level(l + 1)[0])
+        assert np.array_equal(Ac.colidx, H.levels[l + 1].A.colidx)
+        assert rel2(Ac.val, H.levels[l + 1].A.val) <= 1e-12, l
+    return H
+
+
+def test_learned_cold_setup_uses_network_weights_and_matches_oracle():
+    """A model predicting lambda_hat = 8 (above every level's lambda_max, so the guard
+    passes) and omega = 0.3: the setup smooths every prolongator with omega = 0.3, and
+    the oracle's setup given those weights reproduces it; the V-cycle matches too."""
+    m, A, HA, M = _learned_setup(10, 4, _const_model(8.0, 0.3))
+    lam, om, learned = B.amg_setup_weights(M)
+    assert learned.all()
+    assert np.allclose(om[:, 0], 0.3, rtol=1e-6) and np.allclose(lam[:, 0], 8.0, rtol=1e-6)
+    H = _compare_setup_with_oracle(m, A, M, lam, om)
+    r = np.random.default_rng(1).uniform(-1, 1, m.n_dof)
+    z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, dev(r), z)
+    assert rel2(z.cpu().numpy(), OS.vcycle(H, r)) <= 1e-11
+    # the same problem with Lanczos weights has a different prolongator
+    Hl = OS.setup(A, m.coords, m.dirichlet)
+    assert rel2(from_device_bsr(M.level(0)[1]).val, Hl.levels[0].P.val) > 1e-3
+
+
+def test_learned_cold_setup_with_trained_model():
+    """The packaged network in the cold setup of a problem outside its training draws:
+    every level learned (the guard passes), weights within 25 % of the Lanczos
+    setup's, parity with the oracle given those weights, and CG converges."""
+    from paper_2606_24748_amd import train_eigmlp
+    m, A, HA, M = _learned_setup(16, 31, train_eigmlp.load_model())
+    lam, om, learned = B.amg_setup_weights(M)
+    print(f"learned setup: lambda {lam[:, 0].tolist()} omega {om[:, 0].tolist()} learned {learned.tolist()}",
+          flush=True)
+    assert learned.all()
+    H0 = OS.setup(A, m.coords, m.dirichlet)
+    for l in range(M.num_levels() - 1):
+        assert abs(lam[l, 0] / H0.levels[l].lam - 1) <= 0.25, l
+    _compare_setup_with_oracle(m, A, M, lam, om)
+    b = synth.rhs(m, 2)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
+    assert code == B.OK and rel <= 1e-8
+
+
+def test_learned_cold_setup_falls_back_to_lanczos():
+    """A model predicting a far too low lambda_hat fails the growth test on every level:
+    the setup then uses Lanczos and omega = 4 / (3 lambda_hat), bit for bit the plain
+    setup's prolongators."""
+    m, A, HA, M = _learned_setup(10, 5, _const_model(0.05, 0.3))
+    lam, om, learned = B.amg_setup_weights(M)
+    assert not learned.any()
+    o = B.blkamg_opts_default()
+    M0 = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    lam0, om0, le0 = B.amg_setup_weights(M0)
+    assert not le0.any()
+    assert np.array_equal(lam, lam0) and np.array_equal(om, om0)
+    assert np.allclose(om0[:, 0], (4.0 / 3.0) / lam0[:, 0], rtol=1e-15)
+    for l in range(M.num_levels() - 1):
+        assert torch.equal(M.level(l)[1].arrays()[2], M0.level(l)[1].arrays()[2])

@@ -150,3 +150,16 @@ def test_growth_matches_eigendecomposition_and_flags_low_bounds():
         assert abs(g - closed) <= 1e-10 * closed
         assert (g > 1.0) == expect_growth
         assert g <= np.abs(p(lam, lh)).max() * (1 + 1e-12)
+        # power steps: e_k = S^k e_0 in closed form, ratio of the last two A-norms
+        for k in (2, 4):
+            ek = Dm12 @ Q @ np.diag(p(lam, lh) ** k) @ Q.T @ Dp12 @ e0
+            ek1 = Dm12 @ Q @ np.diag(p(lam, lh) ** (k - 1)) @ Q.T @ Dp12 @ e0
+            closed_k = np.sqrt((ek @ Ad @ ek) / (ek1 @ Ad @ ek1))
+            gk = ML.growth(A, Dinv, lh, o, steps=k)
+            assert abs(gk - closed_k) <= 1e-9 * closed_k
+            assert gk <= np.abs(p(lam, lh)).max() * (1 + 1e-12)
+    # a moderately low bound (1/1.25 of lambda_max) amplifies the top of the spectrum:
+    # one application can hide it behind the contracted bulk, power steps show it
+    lh = lmax / 1.25
+    assert np.abs(p(lam, lh)).max() > 1.0
+    assert ML.growth(A, Dinv, lh, o, steps=6) > ML.growth(A, Dinv, lh, o, steps=1)

@@ -6,7 +6,7 @@ import scipy.linalg as sla
 
 import synth
 from oracle import sparse as S
-from oracle import sa
+from oracle import sa, solve
 from oracle.mix import splitmix64, splitmix64_array, start_vector
 
 
@@ -151,3 +151,38 @@ def test_smoothed_prolongator_dense():
     assert np.abs(S.to_dense(P) - ref).max() < 1e-13
     rp, ci = S.structural_product(A.rowptr, A.colidx, A.nbr, A.nbc, Pt.rowptr, Pt.colidx, Pt.nbc)
     assert np.array_equal(P.rowptr, rp) and np.array_equal(P.colidx, ci)
+
+
+def test_smoothed_prolongator_given_weight_and_setup_level_params():
+    """A weight given directly enters P = P~ - omega D^-1 A P~ as is (dense check), and a
+    setup with given (lambda_hat, omega) per level uses them: P on each level equals the
+    dense smoothing with that omega, and the smoother keeps that lambda_hat."""
+    m, A = _problem(4, seed=2)
+    agg, n_agg = sa.aggregate(sa.strength_graph(A, m.dirichlet), m.dirichlet)
+    Pt, _ = sa.tentative_prolongator(agg, n_agg, sa.rigid_body_modes(m.coords))
+    Dinv = S.block_diag_inverse(A)
+    Ad, Ptd = S.to_dense(A), S.to_dense(Pt)
+    for om in (0.3, 0.61):
+        P = sa.smooth_prolongator(A, Pt, Dinv, 2.5, omega=om)
+        ref = Ptd - om * np.linalg.solve(_dense_D(A), Ad @ Ptd)
+        assert np.abs(S.to_dense(P) - ref).max() < 1e-13
+    m, A = _problem(6, seed=4)
+    o = solve.Options(coarse_eq_limit=60)
+    H0 = solve.setup(A, m.coords, m.dirichlet, o)
+    params = [(1.25 * L.lam, 0.9 * o.omega_scale / L.lam) for L in H0.levels[:-1]]
+    H = solve.setup(A, m.coords, m.dirichlet, o, level_params=params)
+    assert H.n_levels == H0.n_levels == 3
+    Pt, _ = sa.tentative_prolongator(H.levels[0].agg, H.levels[0].n_agg, sa.rigid_body_modes(m.coords))
+    ref = S.to_dense(Pt) - params[0][1] * np.linalg.solve(_dense_D(A), S.to_dense(A) @ S.to_dense(Pt))
+    assert np.abs(S.to_dense(H.levels[0].P) - ref).max() < 1e-13
+    for lev, (lam, om) in enumerate(params):
+        L = H.levels[lev]
+        assert L.lam == lam
+        assert np.array_equal(L.agg, H0.levels[lev].agg)
+        # a different weight gives a different prolongator than the method's own
+        assert np.abs(S.to_dense(L.P) - S.to_dense(H0.levels[lev].P)).max() > 1e-6
+    # level_params entries of None keep the method's estimate on that level
+    H1 = solve.setup(A, m.coords, m.dirichlet, o, level_params=[None, params[1]])
+    assert H1.levels[0].lam == H0.levels[0].lam
+    assert np.array_equal(H1.levels[0].P.val, H0.levels[0].P.val)
+    assert H1.levels[1].lam == params[1][0]
