@@ -35,7 +35,9 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Boundaries of the sorted aggregate ids: start[g] = first position holding g (ids
-// are 0..n_agg-1 after the -1 entries; every aggregate is non-empty).
+// are 0..n_agg-1 after the -1 entries; every aggregate is non-empty).  An id at or
+// above n_agg ends the last aggregate early: start[n_agg] is then its position, below
+// n, which the host rejects.  Writes stay inside start[0..n_agg].
 __global__ void agg_starts_kernel(int n, const int32_t* __restrict__ sorted_agg, int32_t n_agg,
                                   int32_t* __restrict__ start) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,8 +45,9 @@ __global__ void agg_starts_kernel(int n, const int32_t* __restrict__ sorted_agg,
   const int32_t g = sorted_agg[i];
   if (g < 0) return;
   const int32_t prev = i > 0 ? sorted_agg[i - 1] : -1;
-  for (int32_t h = prev + 1; h <= g; ++h) start[h] = i;  // ids without members would get a start too
-  if (i == n - 1)
+  const int32_t top = g < n_agg ? g : n_agg;
+  for (int32_t h = prev + 1; h <= top; ++h) start[h] = i;  // ids without members would get a start too
+  if (i == n - 1 && g < n_agg)
     for (int32_t h = g + 1; h <= n_agg; ++h) start[h] = n;
 }
 
@@ -196,6 +199,7 @@ bool tentative_device(int32_t nbr, int32_t bs, const int32_t* d_agg, int32_t n_a
   HIP_CHECK(hipGetLastError());
   std::vector<int32_t> st = download(start.p, start.n, s);
   int32_t m_max = 0;
+  BLK_REQUIRE(st[n_agg] == nbr, BLKAMG_EINVAL, "aggregate id at or above n_agg");
   for (int32_t g = 0; g < n_agg; ++g) {
     BLK_REQUIRE(st[g] >= 0 && st[g + 1] >= st[g], BLKAMG_EINVAL, "aggregate ids must be 0..n_agg-1, each used");
     m_max = std::max(m_max, (st[g + 1] - st[g]) * bs);

@@ -59,7 +59,10 @@ def _check_levels(M, H, lam_tol=1e-12, val_tol=1e-12):
         HAl, HPl = M.level(lev)
         Al = from_device_bsr(HAl)
         smoothed = st == 1
-        assert np.all(np.diff(np.where(smoothed, 0, 1)) >= 0)  # smoothed instances first
+        # in row order, the level's smoothed instances come before those that end on it
+        pres = np.flatnonzero(st > 0)
+        in_rows = st[pres[np.argsort(r0[pres], kind="stable")]]
+        assert np.all(np.diff(np.where(in_rows == 1, 0, 1)) >= 0)
         agg = M.aggregates(lev) if smoothed.any() else None
         Pl = from_device_bsr(HPl) if HPl is not None else None
         if lev + 1 < nl:

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 import synth  # noqa: E402
 from oracle import sparse as S  # noqa: E402
 from paper_2606_24748_amd import blkamg as B  # noqa: E402
-from tests.gpu_util import rel2  # noqa: E402
+from tests.gpu_util import from_device_bsr, rel2  # noqa: E402
 
 N = 128
 

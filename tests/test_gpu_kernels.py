@@ -83,11 +83,14 @@ def test_spmv_empty_and_errors():
     y = torch.ones(15, dtype=torch.float64, device="cuda")
     B.bsr_spmv(H, 1.0, torch.zeros(12, dtype=torch.float64, device="cuda"), 2.0, y)
     assert torch.all(y == 2.0)
-    with pytest.raises(B.BlkAmgError) as e:
+    # vectors of the wrong element type are refused on the host, before any launch
+    with pytest.raises(ValueError):
         B.bsr_spmv(H, 1.0, torch.zeros(12, device="cuda"), 0.0, torch.zeros(15, device="cuda"))
-    assert e.value.code == B.EINVAL
-    with pytest.raises(B.BlkAmgError):
+    with pytest.raises(ValueError):
         B.bsr_spmv(H, 1.0, torch.zeros(12, dtype=torch.float64, device="cuda"), 0.0, y, nrhs=9)
+    # the library itself refuses the same calls (no launch)
+    assert B._lib.bsr_spmv(H.h, 1.0, B._ptr(y), 0.0, B._ptr(y), B.F64, 9, None) == B.EINVAL
+    assert B._lib.bsr_spmv(H.h, 1.0, B._ptr(y), 0.0, B._ptr(y), 7, 1, None) == B.EINVAL
 
 
 def test_coo_plan_bit_exact_and_values():
