@@ -196,25 +196,49 @@ def finish_cpu_baseline(proc, timeout: float = 600.0) -> dict | None:
 # ----------------------------------------------------------------------------------
 # GPU benchmark
 # ----------------------------------------------------------------------------------
-def spmv_probe(B, RL, torch, plan, HA, vals0, n_dof, a_inf, reps, stream):
-    """Average duration of the fine 3x3 FP64 bsr_spmv, timed with HIP events on the
-    stream it is launched on, and its algorithmic bandwidth."""
-    B.coo_assemble_blocked(plan, vals0, B.INSERT, HA)
-    xv = torch.rand(n_dof, dtype=torch.float64, device="cuda")
-    yv = torch.zeros(n_dof, dtype=torch.float64, device="cuda")
+def _time_launches(torch, stream, fn, reps):
     for _ in range(3):
-        B.bsr_spmv(HA, 1.0, xv, 0.0, yv)
+        fn()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(reps):
-        B.bsr_spmv(HA, 1.0, xv, 0.0, yv)
+        fn()
     e1.record(stream)
     e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    nbytes = RL.spmv_bytes(a_inf["nbr"], a_inf["nbc"], 3, 3, a_inf["nnzb"], 8, 8)
-    return {"avg_launch_ms": ms, "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
-            "reps": reps}
+    return e0.elapsed_time(e1) / reps
+
+
+def spmv_probe(B, RL, torch, plan, HA, vals0, n_dof, a_inf, reps, stream):
+    """Average durations of the fine 3x3 SpMVs, timed with HIP events on the stream they
+    are launched on, with their algorithmic bandwidth: bsr_spmv (every block read) and
+    bsr_spmv_sym (the symmetric reads the hierarchy and CG use: diagonal and upper
+    blocks from memory, lower blocks as transposed mirrors), in FP64 and on an FP32 copy
+    of the operator."""
+    B.coo_assemble_blocked(plan, vals0, B.INSERT, HA)
+    rp, ci, v = HA.arrays()
+    rows = torch.repeat_interleave(torch.arange(a_inf["nbr"], device="cuda"), (rp[1:] - rp[:-1]).long())
+    n_lower = int((ci.long() < rows).sum())
+    n_upper = a_inf["nnzb"] - n_lower
+    del rows
+    H32 = B.bsr_create(a_inf["nbr"], a_inf["nbc"], 3, 3, rp, ci, v.to(torch.float32).contiguous())
+    del v
+    out = {"reps": reps, "n_upper_blocks": n_upper, "n_lower_blocks": n_lower}
+    for tag, H, dt, s in (("f64", HA, torch.float64, 8), ("f32", H32, torch.float32, 4)):
+        xv = torch.rand(n_dof, dtype=dt, device="cuda")
+        yv = torch.zeros(n_dof, dtype=dt, device="cuda")
+        ms = _time_launches(torch, stream, lambda: B.bsr_spmv(H, 1.0, xv, 0.0, yv), reps)
+        ms_sym = _time_launches(torch, stream, lambda: B.bsr_spmv_sym(H, 1.0, xv, 0.0, yv), reps)
+        nb = RL.spmv_bytes(a_inf["nbr"], a_inf["nbc"], 3, 3, a_inf["nnzb"], s, s)
+        nb_sym = RL.spmv_sym_bytes(a_inf["nbr"], 3, n_upper, n_lower, s, s)
+        out[tag] = {"full": {"avg_launch_ms": ms, "bytes_per_launch": nb, "achieved_GBs": nb / (ms * 1e-3) / 1e9},
+                    "sym": {"avg_launch_ms": ms_sym, "bytes_per_launch": nb_sym,
+                            "achieved_GBs": nb_sym / (ms_sym * 1e-3) / 1e9,
+                            "full_equivalent_GBs": nb / (ms_sym * 1e-3) / 1e9}}
+        log(f"[spmv probe] {tag}: full {ms:.3f} ms ({nb / (ms * 1e-3) / 1e9:.0f} GB/s), symmetric reads "
+            f"{ms_sym:.3f} ms ({nb_sym / (ms_sym * 1e-3) / 1e9:.0f} GB/s on {nb_sym / 1e9:.2f} GB)")
+    del H32
+    return out
 
 
 def copy_probe(torch, stream, nbytes=1 << 30, reps=10):
@@ -329,10 +353,13 @@ def run_q2(args, B, RL, torch, dev, stream):
         r.pop("_x", None)
         res[var] = r
     probe = spmv_probe(B, RL, torch, plan, HA, vals[0], mesh.n_dof, a_inf, args.probe_reps, stream)
-    probe["frac"] = probe["achieved_GBs"] / RL.HBM_PEAK_GBS
+    for tag in ("f64", "f32"):
+        for mode in ("full", "sym"):
+            probe[tag][mode]["frac"] = probe[tag][mode]["achieved_GBs"] / RL.HBM_PEAK_GBS
     res["spmv"] = probe
-    log(f"[q2] fine SpMV {probe['avg_launch_ms']:.3f} ms, {probe['achieved_GBs']:.0f} GB/s "
-        f"({100 * probe['frac']:.1f}% of HBM peak)")
+    p64 = probe["f64"]
+    log(f"[q2] fine FP64 SpMV {p64['full']['avg_launch_ms']:.3f} ms ({100 * p64['full']['frac']:.1f}% of HBM peak), "
+        f"symmetric reads {p64['sym']['avg_launch_ms']:.3f} ms ({100 * p64['sym']['frac']:.1f}%)")
     del plan, HA, vals
     torch.cuda.synchronize()
     return res
@@ -800,7 +827,10 @@ def main(argv=None):
         torch.cuda.empty_cache()
     if not args.no_batch:
         side["batch"] = run_batch(args, B, torch, dev, stream)
-    achieved, spmv_b, spmv_ms = probe["achieved_GBs"], probe["bytes_per_launch"], probe["avg_launch_ms"]
+    # the roofline kernel: the fine FP64 SpMV with symmetric reads, the one CG and the
+    # FP64 V-cycle run (full reads beside it)
+    psym, pfull = probe["f64"]["sym"], probe["f64"]["full"]
+    achieved, spmv_b, spmv_ms = psym["achieved_GBs"], psym["bytes_per_launch"], psym["avg_launch_ms"]
 
     head = "fp64" if "fp64" in results else variants[0]
     hr = results[head]
@@ -835,8 +865,11 @@ def main(argv=None):
         "pcg_its": statistics.median(hr["iterations"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / RL.HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "bsr_spmv fine 3x3 f64 (spmv_kernel<3,3,1,32,1,double,double,double,EpiAxpby>)",
-                     "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms},
+                     "kernel": ("bsr_spmv_sym fine 3x3 f64, symmetric reads "
+                                "(spmv_kernel<3,3,1,32,1,double,double,double,EpiAxpby,true>)"),
+                     "bytes_per_launch": spmv_b, "avg_launch_ms": spmv_ms,
+                     "full_reads": {"avg_launch_ms": pfull["avg_launch_ms"], "bytes_per_launch": pfull["bytes_per_launch"],
+                                    "frac": pfull["achieved_GBs"] / RL.HBM_PEAK_GBS}},
         "ptap_roofline": _ptap_roofline(RL, hr),
         "copy_GBs": copy["GBs"],
         "coo_plan_ms": {"host": 1e3 * t_plan, "device": 1e3 * plan_dev["device_s"]},

@@ -135,6 +135,18 @@ int bsr_arrays(bsr_t A, const int32_t** d_rowptr, const int32_t** d_colidx, void
  * beta == 0 overwrites y (NaNs in y are not propagated).  Async. */
 int bsr_spmv(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
              int vec_dtype, int32_t nrhs, void* stream);
+/* y = alpha * S x + beta * y for a square-blocked matrix with a structurally
+ * symmetric pattern, S the symmetric completion of A's upper triangle: S_ij = A_ij
+ * for j >= i and A_ji^T for j < i (S = A when A is symmetric, as the SPD operators
+ * of CG are; paper §2.1, §4.1).  Only the diagonal and upper blocks are streamed from
+ * memory; a strictly lower block is read as the transpose of its mirror, which the
+ * mirror's own row read shortly before, so the second read is mostly served from the
+ * caches.  For symmetric A the result is that of bsr_spmv up to the grouping of the
+ * row sums (its own lane shape).  Arguments as bsr_spmv (nrhs > 1 reads every block).  The mirror index (int32 per block) is built
+ * on the first call (device, sync, allocates).  EINVAL if A is not square-blocked or
+ * its pattern is not symmetric.  Async afterwards. */
+int bsr_spmv_sym(bsr_t A, double alpha, const void* d_x, double beta, void* d_y,
+                 int vec_dtype, int32_t nrhs, void* stream);
 /* y = alpha * A^T x + beta * y through a cached explicit transpose R = A^T
  * (the cached restriction of paper §3.5).  x: [nbr*bs_r][nrhs],
  * y: [nbc*bs_c][nrhs].  The transpose pattern is built on the first call (sync,
@@ -299,6 +311,15 @@ typedef struct {
   const float* eig_model;   /* host copy of a model (BLKAMG_MLP_MODEL floats) used from
                                the cold setup on when eig_mode is BLKAMG_EIG_MLP (copied;
                                NULL = none until amg_set_eig_model).  Default NULL */
+  int32_t sym_spmv;         /* 1 (default): the hierarchy's SpMVs on FP64 level operators
+                               (smoother, residual, Lanczos, growth test) and pcg_solve's
+                               A p read only the diagonal and upper blocks of a
+                               structurally symmetric operator from memory and use each
+                               strictly lower block as the transpose of its mirror, i.e.
+                               they apply the symmetric completion of the upper triangle
+                               (A itself when A is symmetric, as CG requires; the results
+                               then differ from full reads only in the grouping of the row
+                               sums).  0: read every block */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */

@@ -83,6 +83,25 @@ def spmv_t(A: Bsr, x: np.ndarray, alpha: float = 1.0, beta: float = 0.0, y=None)
     return out
 
 
+def symmetric_completion(A: Bsr) -> Bsr:
+    """The matrix S with A's pattern, A's diagonal and upper blocks (block column >= block
+    row), and each strictly lower block replaced by the transpose of its mirror:
+    S_IJ = A_JI^T for J < I.  Defined for square blocks and a symmetric pattern; S = A
+    exactly when A is symmetric (the SPD operators CG is applied to, paper §2.1, §4.1).
+    Plain loop over the blocks with a dictionary of positions."""
+    assert A.br == A.bc and A.nbr == A.nbc, "square blocks and a square matrix"
+    pos = {}
+    for r in range(A.nbr):
+        for k in range(int(A.rowptr[r]), int(A.rowptr[r + 1])):
+            pos[(r, int(A.colidx[k]))] = k
+    val = A.val.copy()
+    for (r, c), k in pos.items():
+        if c < r:
+            assert (c, r) in pos, "pattern is not symmetric"
+            val[k] = A.val[pos[(c, r)]].T
+    return A.with_values(val)
+
+
 def spmv_rows(A: Bsr, x: np.ndarray, rows) -> np.ndarray:
     """(A x) restricted to the given block rows, by the definition sum_J A_IJ x_J."""
     xb = x.reshape(A.nbc, A.bc)

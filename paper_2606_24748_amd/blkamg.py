@@ -62,6 +62,7 @@ class Opts(C.Structure):
         ("agg_seed", C.c_uint64),
         ("growth_steps", C.c_int32),
         ("eig_model", C.c_void_p),
+        ("sym_spmv", C.c_int32),
     ]
 
 
@@ -76,6 +77,7 @@ _SIG = {
     "bsr_arrays": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p)]),
     "bsr_spmv": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_spmv_t": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
+    "bsr_spmv_sym": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_autotune": (C.c_int, [_p, C.c_int, _i32, _p, _pi32]),
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
     "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
@@ -290,6 +292,14 @@ def bsr_spmv(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
     _spmv_args(A, x, y, nrhs, False)
     _check(_lib.bsr_spmv(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs, _stream(stream)),
            "bsr_spmv")
+
+
+def bsr_spmv_sym(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):
+    """y = alpha S x + beta y, S the symmetric completion of A's upper triangle (A itself
+    when A is symmetric), reading only the diagonal and upper blocks from memory."""
+    _spmv_args(A, x, y, nrhs, False)
+    _check(_lib.bsr_spmv_sym(A.h, float(alpha), _ptr(x), float(beta), _ptr(y), dtype_code(y), nrhs,
+                             _stream(stream)), "bsr_spmv_sym")
 
 
 def bsr_spmv_t(A: Bsr, alpha, x, beta, y, nrhs=1, stream=None):

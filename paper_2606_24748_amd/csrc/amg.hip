@@ -42,6 +42,8 @@ struct Level {
   DevBuf<int32_t> d_act_off;           // block-row offsets of the smoothed segments
   DevBuf<uint16_t> d_row_seg;          // segment of each smoothed row (several segments only)
   SegGrid lgrid;                       // Lanczos dots over the smoothed dofs
+  const int32_t* mir = nullptr;        // symmetric-read mirror index of A (nullptr = full reads)
+  int sym_dist = 0;                    // A's typical lower bandwidth (workgroup runs of the symmetric reads)
   DevBuf<char> dinv;                   // [act_rows][bs][bs] hierarchy dtype
   DevBuf<int32_t> diag_idx;
   DevBuf<char> f, out, x, r, d, d2;    // work vectors [rows][vec_nr] (hierarchy dtype)
@@ -378,10 +380,10 @@ void lanczos_bs(amg_s* M, int l, hipStream_t s) {
   lanczos_scale_kernel<BS, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, sc, -1, V[iwu], V[iwy], V[iu], V[iy]);
   HIP_CHECK(hipGetLastError());
   const int k = M->o.lanczos_steps;
-  const int G = lanes_for(A, 1);
+  const int G = lanes_for_reads(A, 1, L.mir);
   for (int step = 0; step < k; ++step) {
     EpiLanczos<TV, TV> epi{V[iy_prev], V[iwy], sc, off, ns, step};
-    launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, V[iu], epi, s);
+    launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, V[iu], epi, s, L.mir, L.sym_dist);
     seg_reduce<1>(M, L.lgrid, V[iu], V[iwy], OpLzAlpha{sc, step}, s);
     if (step == k - 1) break;
     lanczos_orth_kernel<BS, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, sc, step, V[iy], V[iwy], dinv, V[iwu]);
@@ -459,11 +461,12 @@ void coarse_apply(Level& L, const TV* f, TV* out, hipStream_t s) {
 // V-cycle
 // ---------------------------------------------------------------------------
 template <int MODE, int NR, class TV>
-void smooth(const bsr_s* A, const TV* gather, const EpiSmooth<MODE, TV, TV>& epi, hipStream_t s) {
-  const int code = lanes_for(A, NR);
+void smooth(const bsr_s* A, const int32_t* mir, int sym_dist, const TV* gather, const EpiSmooth<MODE, TV, TV>& epi,
+            hipStream_t s) {
+  const int code = lanes_for_reads(A, NR, mir);
   const auto* v = static_cast<const TV*>(A->val);
-  if (A->br == 3) launch_rows<3, 3, NR, TV, TV, TV>(code, A->nbr, A->rowptr, A->colidx, v, gather, epi, s);
-  else launch_rows<6, 6, NR, TV, TV, TV>(code, A->nbr, A->rowptr, A->colidx, v, gather, epi, s);
+  if (A->br == 3) launch_rows<3, 3, NR, TV, TV, TV>(code, A->nbr, A->rowptr, A->colidx, v, gather, epi, s, mir, sym_dist);
+  else launch_rows<6, 6, NR, TV, TV, TV>(code, A->nbr, A->rowptr, A->colidx, v, gather, epi, s, mir, sym_dist);
 }
 
 template <class TV, int NR>
@@ -490,13 +493,13 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
     const bool last = (t == k - 1);
     EpiSmooth<M_STEP, TV, TV> e{t == 1 ? f : r, last ? nullptr : r, d, last ? nullptr : d2, t == 1 ? d : x, x,
                                 dinv, sc, rseg, t - 1};
-    smooth<M_STEP, NR, TV>(A, d, e, s);
+    smooth<M_STEP, NR, TV>(A, L.mir, L.sym_dist, d, e, s);
     std::swap(d, d2);
   }
   // residual and restriction
   {
     EpiSmooth<M_RESID, TV, TV> e{f, r, nullptr, nullptr, nullptr, nullptr, dinv, sc, rseg, 0};
-    smooth<M_RESID, NR, TV>(A, x, e, s);
+    smooth<M_RESID, NR, TV>(A, L.mir, L.sym_dist, x, e, s);
   }
   Level& C = *M->lv[l + 1];
   TV* fc = buf<TV>(C.f);
@@ -508,12 +511,12 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
   // post-smoothing from x
   {
     EpiSmooth<M_INITX, TV, TV> e{f, r, nullptr, d, x, out, dinv, sc, rseg, 0};
-    smooth<M_INITX, NR, TV>(A, x, e, s);
+    smooth<M_INITX, NR, TV>(A, L.mir, L.sym_dist, x, e, s);
   }
   for (int t = 1; t < k; ++t) {
     const bool last = (t == k - 1);
     EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, d, last ? nullptr : d2, out, out, dinv, sc, rseg, t - 1};
-    smooth<M_STEP, NR, TV>(A, d, e, s);
+    smooth<M_STEP, NR, TV>(A, L.mir, L.sym_dist, d, e, s);
     std::swap(d, d2);
   }
 }
@@ -712,7 +715,7 @@ std::vector<double> judge_level_bs(amg_s* M, int l, int k, hipStream_t s) {
   const int32_t* off = L.d_act_off.p;
   const TM* val = static_cast<const TM*>(A->val);
   const TM* dinv = reinterpret_cast<const TM*>(L.dinv.p);
-  const int G = lanes_for(A, 1);
+  const int G = lanes_for_reads(A, 1, L.mir);
   lanczos_start_kernel<BS, TM, double><<<vgrid(nbr), 256, 0, s>>>(
       nbr, off, ns, M->o.lanczos_seed + static_cast<uint64_t>(l), val, L.diag_idx.p, wu.p, wy.p);
   seg_reduce<1>(M, L.lgrid, wu.p, wy.p, OpLzSqrt{jsc.p, -1}, s);
@@ -722,7 +725,7 @@ std::vector<double> judge_level_bs(amg_s* M, int l, int k, hipStream_t s) {
     double* u = U.p + static_cast<size_t>(step) * n;
     double* y = Y.p + static_cast<size_t>(step) * n;
     launch_rows<BS, BS, 1, TM, double, double>(G, nbr, A->rowptr, A->colidx, val, u,
-                                                EpiAxpby<double, double>{wy.p, 1.0, 0.0}, s);
+                                                EpiAxpby<double, double>{wy.p, 1.0, 0.0}, s, L.mir, L.sym_dist);
     seg_reduce<1>(M, L.lgrid, u, wy.p, OpLzAlpha{jsc.p, step}, s);
     if (step == k - 1) break;
     judge_orth_kernel<BS><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, jsc.p, step, y, step > 0 ? y - n : nullptr, wy.p);
@@ -785,17 +788,18 @@ void growth_level_bs(amg_s* M, int l, hipStream_t s) {
   HIP_CHECK(hipMemsetAsync(zero, 0, n * sizeof(TV), s));
   lanczos_start_kernel<BS, TV, TV><<<vgrid(nbr), 256, 0, s>>>(nbr, off, ns, kGrowthSeed, val, L.diag_idx.p, e0, scratch);
   HIP_CHECK(hipGetLastError());
-  const int G = lanes_for(A, 1);
+  const int G = lanes_for_reads(A, 1, L.mir);
   const int K = std::max(1, M->o.growth_steps);
   for (int step = 0; step < K; ++step) {
     if (step > 0) HIP_CHECK(hipMemcpyAsync(e0, x, n * sizeof(TV), hipMemcpyDeviceToDevice, s));
     if (step == K - 1) {
-      launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
+      launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, e0, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s,
+                                         L.mir, L.sym_dist);
       seg_reduce<1>(M, L.lgrid, e0, w, OpStoreTmp{sc, 1}, s);
     }
     {
       EpiSmooth<M_INITX, TV, TV> e{zero, r, nullptr, d, e0, x, dinv, sc, L.d_row_seg.p, 0};
-      smooth<M_INITX, 1, TV>(A, e0, e, s);
+      smooth<M_INITX, 1, TV>(A, L.mir, L.sym_dist, e0, e, s);
     }
     TV* dd = d;
     TV* dd2 = d2;
@@ -803,11 +807,12 @@ void growth_level_bs(amg_s* M, int l, hipStream_t s) {
       const bool last = (t == M->o.cheb_degree - 1);
       EpiSmooth<M_STEP, TV, TV> e{r, last ? nullptr : r, dd, last ? nullptr : dd2, x, x, dinv, sc, L.d_row_seg.p,
                                   t - 1};
-      smooth<M_STEP, 1, TV>(A, dd, e, s);
+      smooth<M_STEP, 1, TV>(A, L.mir, L.sym_dist, dd, e, s);
       std::swap(dd, dd2);
     }
   }
-  launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, x, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s);
+  launch_rows<BS, BS, 1, TV, TV, TV>(G, nbr, A->rowptr, A->colidx, val, x, EpiAxpby<TV, TV>{w, TV(1), TV(0)}, s,
+                                     L.mir, L.sym_dist);
   seg_reduce<1>(M, L.lgrid, x, w, OpStoreTmp{sc, 2}, s);
 }
 
@@ -1040,6 +1045,7 @@ void check_opts(const blkamg_opts& o) {
   BLK_REQUIRE(o.eig_mode == BLKAMG_EIG_LANCZOS || o.eig_mode == BLKAMG_EIG_MLP, BLKAMG_EINVAL, "bad eig_mode");
   BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || o.agg_mode == BLKAMG_AGG_LUBY, BLKAMG_EINVAL, "bad agg_mode");
   BLK_REQUIRE(o.growth_steps >= 1 && o.growth_steps <= 16, BLKAMG_EINVAL, "growth_steps must be in 1..16");
+  BLK_REQUIRE(o.sym_spmv == 0 || o.sym_spmv == 1, BLKAMG_EINVAL, "sym_spmv must be 0 or 1");
 }
 
 // Validate and copy a model to the device (the caller's array is not kept).
@@ -1091,6 +1097,14 @@ void finish_setup(amg_s* M, hipStream_t s) {
   }
   ensure_vectors(M, 1);
   map_samples(M);
+  // symmetric reads of every smoothed level operator (its prefix view shares the arrays
+  // and so the mirror index)
+  for (auto& L : M->lv) {
+    // FP64 operators only: on FP32 blocks the scattered mirror reads cost more than the
+    // bytes they save (fine 3x3 at 128^3: 0.49 ms against 0.45 ms for full reads)
+    L->mir = (M->o.sym_spmv && L->n_act > 0 && L->A->dtype == BLKAMG_F64) ? symmetric_mirror(L->A, s) : nullptr;
+    L->sym_dist = L->mir ? L->A->sym_dist : 0;
+  }
   smoother_refresh(M, nullptr, s);
   if (M->o.autotune_nrhs > 0) autotune_hierarchy(M, M->o.autotune_nrhs, s);
   HIP_CHECK(hipStreamSynchronize(s));
@@ -1358,14 +1372,17 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
     reduce(M, vg, sc + S_RZ, R_STORE, s);
     direction(z32, 0);
   }
-  const int G = lanes_for(A, 1);
+  const int32_t* mir = M->o.sym_spmv ? symmetric_mirror(A, s) : nullptr;
+  const int G = lanes_for_reads(A, 1, mir);
   bool converged = false;
   while (it < maxit) {
     EpiPcgW epi{p, w, M->partial.p};
     const int sg = A->br == 3 ? launch_rows<3, 3, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
-                                                                            static_cast<const double*>(A->val), p, epi, s)
+                                                                            static_cast<const double*>(A->val), p, epi, s,
+                                                                            mir, A->sym_dist)
                               : launch_rows<6, 6, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
-                                                                            static_cast<const double*>(A->val), p, epi, s);
+                                                                            static_cast<const double*>(A->val), p, epi, s,
+                                                                            mir, A->sym_dist);
     reduce(M, sg, nullptr, R_ALPHA, s);
     pcg_update_kernel<<<vg, 256, 0, s>>>(n, sc, p, w, d_x, r, M->partial.p, r32);
     HIP_CHECK(hipGetLastError());
@@ -1569,6 +1586,7 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->agg_seed = 0x4D495332ull;
   o->growth_steps = 3;
   o->eig_model = nullptr;
+  o->sym_spmv = 1;
 }
 
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream,

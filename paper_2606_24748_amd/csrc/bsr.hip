@@ -125,25 +125,28 @@ __global__ void spmv_generic_kernel(int nbr, int br, int bc, int nrhs, const int
 }
 
 template <int BR, int BC, class TM, class TX, class TA>
-void spmv_fast(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code = 0) {
+void spmv_fast(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code,
+               const int32_t* mir, int sym_dist) {
   const int G = code ? code : lanes_for(A, nrhs);
   const auto* v = static_cast<const TM*>(A->val);
   if (nrhs == 1) {
-    launch_rows<BR, BC, 1, TM, TX, TA>(G, A->nbr, A->rowptr, A->colidx, v, x, EpiAxpby<TX, TA>{y, alpha, beta}, s);
+    launch_rows<BR, BC, 1, TM, TX, TA>(G, A->nbr, A->rowptr, A->colidx, v, x, EpiAxpby<TX, TA>{y, alpha, beta}, s,
+                                       mir, sym_dist);
   } else {
     launch_rows<BR, BC, 8, TM, TX, TA>(G, A->nbr, A->rowptr, A->colidx, v, x, EpiAxpby<TX, TA>{y, alpha, beta}, s);
   }
 }
 
 template <class TM, class TX, class TA>
-void spmv_typed(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code) {
+void spmv_typed(const bsr_s* A, TA alpha, const TX* x, TA beta, TX* y, int nrhs, hipStream_t s, int code,
+                const int32_t* mir, int sym_dist) {
   if (A->nbr == 0) return;
   const int br = A->br, bc = A->bc;
   if (nrhs == 1 || nrhs == 8) {
-    if (br == 3 && bc == 3) return spmv_fast<3, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
-    if (br == 3 && bc == 6) return spmv_fast<3, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
-    if (br == 6 && bc == 3) return spmv_fast<6, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
-    if (br == 6 && bc == 6) return spmv_fast<6, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code);
+    if (br == 3 && bc == 3) return spmv_fast<3, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code, mir, sym_dist);
+    if (br == 3 && bc == 6) return spmv_fast<3, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code, nullptr, 0);
+    if (br == 6 && bc == 3) return spmv_fast<6, 3, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code, nullptr, 0);
+    if (br == 6 && bc == 6) return spmv_fast<6, 6, TM, TX, TA>(A, alpha, x, beta, y, nrhs, s, code, mir, sym_dist);
   }
   const int64_t total = static_cast<int64_t>(A->nbr) * br * nrhs;
   const int grid = static_cast<int>(std::min<int64_t>((total + 255) / 256, 1 << 20));
@@ -191,19 +194,19 @@ void cast_values(const void* src, int sdt, void* dst, int ddt, size_t n, hipStre
 }
 
 void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs, hipStream_t s,
-          int code) {
+          int code, const int32_t* mir, int sym_dist) {
   BLK_REQUIRE(nrhs >= 1 && nrhs <= 8, BLKAMG_EINVAL, "nrhs must be in 1..8");
   if (A->nbr > 0) BLK_REQUIRE(y != nullptr, BLKAMG_EINVAL, "y is NULL");
   if (A->nnzb > 0) BLK_REQUIRE(x != nullptr, BLKAMG_EINVAL, "x is NULL");
   if (A->dtype == BLKAMG_F64 && vdt == BLKAMG_F64) {
     spmv_typed<double, double, double>(A, alpha, static_cast<const double*>(x), beta, static_cast<double*>(y), nrhs, s,
-                                       code);
+                                       code, mir, sym_dist);
   } else if (A->dtype == BLKAMG_F32 && vdt == BLKAMG_F32) {
     spmv_typed<float, float, float>(A, static_cast<float>(alpha), static_cast<const float*>(x),
-                                    static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code);
+                                    static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code, mir, sym_dist);
   } else if (A->dtype == BLKAMG_BF16 && vdt == BLKAMG_F32) {
     spmv_typed<bf16, float, float>(A, static_cast<float>(alpha), static_cast<const float*>(x),
-                                   static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code);
+                                   static_cast<float>(beta), static_cast<float*>(y), nrhs, s, code, mir, sym_dist);
   } else {
     fail(BLKAMG_EINVAL, "unsupported matrix/vector dtype combination");
   }
@@ -242,6 +245,70 @@ int autotune_lanes(bsr_s* A, int vdt, int nrhs, hipStream_t s) {
   (void)hipEventDestroy(e1);
   A->tuned[nrhs > 1 ? 1 : 0] = best;
   return best;
+}
+
+// One thread per block row: every strictly lower block (row, c) finds its mirror
+// (c, row) by binary search in row c (columns ascending); a missing mirror clears
+// *ok (a row with unsorted columns can only fail the search, so every entry
+// written is a valid block position).
+__global__ void sym_mirror_kernel(int nbr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  int32_t* __restrict__ mir, int* __restrict__ ok, int32_t* __restrict__ dist) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nbr) return;
+  int far = 0;
+  for (int k = rp[row]; k < rp[row + 1]; ++k) {
+    const int c = ci[k];
+    if (c >= row) {
+      mir[k] = k;  // upper part: read in place (entry unused)
+      continue;
+    }
+    int lo = rp[c], hi = rp[c + 1], at = -1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const int v = ci[mid];
+      if (v == row) { at = mid; break; }
+      if (v < row) lo = mid + 1; else hi = mid;
+    }
+    if (at < 0) *ok = 0;
+    mir[k] = at < 0 ? k : at;  // a valid block position either way
+    far = max(far, row - c);
+  }
+  dist[row] = far;
+}
+
+const int32_t* symmetric_mirror(bsr_s* A, hipStream_t s) {
+  if (A->sym_state == 0) {
+    A->sym_state = -1;
+    if (A->br == A->bc && A->nbr == A->nbc && A->nnzb > 0) {
+      A->sym_mir.alloc(static_cast<size_t>(A->nnzb));
+      DevBuf<int> ok(1);
+      DevBuf<int32_t> dist(static_cast<size_t>(A->nbr));
+      const int one = 1;
+      HIP_CHECK(hipMemcpyAsync(ok.p, &one, sizeof(int), hipMemcpyHostToDevice, s));
+      sym_mirror_kernel<<<(A->nbr + 255) / 256, 256, 0, s>>>(A->nbr, A->rowptr, A->colidx, A->sym_mir.p, ok.p,
+                                                              dist.p);
+      HIP_CHECK(hipGetLastError());
+      int h = 0;
+      HIP_CHECK(hipMemcpyAsync(&h, ok.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      std::vector<int32_t> d = download(dist.p, dist.n, s);
+      if (h) {
+        A->sym_state = 1;
+        std::nth_element(d.begin(), d.begin() + d.size() / 2, d.end());
+        A->sym_dist = d[d.size() / 2];
+      } else {
+        A->sym_mir.release();
+      }
+    }
+  }
+  return A->sym_state == 1 ? A->sym_mir.p : nullptr;
+}
+
+int lanes_for_reads(const bsr_s* A, int nrhs, const int32_t* mir) {
+  // symmetric reads of 3x3 blocks: 16 lanes per row, two blocks per lane and step
+  // (measured on the fine FP64 operator at 128^3: 0.768 ms against 0.79-0.83 ms with
+  // 32 x 1, 32 x 2, 8 x 1-2 and 1.1 ms with 64 lanes)
+  if (mir && nrhs == 1 && A->br == 3 && A->tuned[0] == 0) return lane_code(16, 2);
+  return lanes_for(A, nrhs);
 }
 
 bsr_s* transpose_of(bsr_s* A, hipStream_t s) {
@@ -419,6 +486,17 @@ int bsr_spmv(bsr_t A, double alpha, const void* d_x, double beta, void* d_y, int
   BLK_API_BEGIN
   BLK_REQUIRE(A != nullptr, BLKAMG_EINVAL, "A is NULL");
   spmv(A, alpha, d_x, beta, d_y, vec_dtype, nrhs, as_stream(stream));
+  BLK_API_END
+}
+
+int bsr_spmv_sym(bsr_t A, double alpha, const void* d_x, double beta, void* d_y, int vec_dtype, int32_t nrhs,
+                 void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(A != nullptr, BLKAMG_EINVAL, "A is NULL");
+  hipStream_t s = as_stream(stream);
+  const int32_t* mir = symmetric_mirror(A, s);
+  BLK_REQUIRE(mir != nullptr, BLKAMG_EINVAL, "symmetric reads need square blocks and a symmetric pattern");
+  spmv(A, alpha, d_x, beta, d_y, vec_dtype, nrhs, s, lanes_for_reads(A, nrhs, mir), mir, A->sym_dist);
   BLK_API_END
 }
 

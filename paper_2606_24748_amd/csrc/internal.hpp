@@ -31,6 +31,11 @@ struct bsr_s {
   uint64_t stamp = 1;  // value-state stamp
   int tuned[2] = {0, 0};  // autotuned SpMV lane code for 1 and for 8 right-hand sides (0 = heuristic)
   std::unique_ptr<blk::TransposeCache> tcache;
+  // symmetric reads: mirror position of every strictly lower block (built once, on the
+  // device; sym_state 0 = not built, 1 = built, -1 = pattern not symmetric)
+  blk::DevBuf<int32_t> sym_mir;
+  int sym_state = 0;
+  int sym_dist = 0;  // median over rows of the distance to the row's first lower column
   // host copy of the pattern (filled on demand or at creation)
   std::vector<int32_t> h_rowptr, h_colidx;
   bool h_pattern = false;
@@ -51,13 +56,21 @@ std::unique_ptr<bsr_s> make_owned(int32_t nbr, int32_t nbc, int32_t br, int32_t 
 void ensure_host_pattern(bsr_s* A);
 // Transpose cache of A, built if needed; values refreshed on `s` if stale.
 bsr_s* transpose_of(bsr_s* A, hipStream_t s);
+// Mirror index of A's strictly lower blocks for the symmetric SpMV reads (position
+// of block (colidx[k], row) for every block k with colidx[k] < row), built once on
+// the device; nullptr when A is not square-blocked or its pattern is not symmetric.
+// Sync on the first call.
+const int32_t* symmetric_mirror(bsr_s* A, hipStream_t s);
 // y = alpha op(A) x + beta y
 // (code != 0 forces that lane configuration)
+// (mir: symmetric reads with that mirror index, one right-hand side; see row_product)
 void spmv(const bsr_s* A, double alpha, const void* x, double beta, void* y, int vdt, int nrhs,
-          hipStream_t s, int code = 0);
+          hipStream_t s, int code = 0, const int32_t* mir = nullptr, int sym_dist = 0);
 // SpMV lane configuration (G * 8 + U) for A with nrhs right-hand sides: the
 // autotuned one if present, else a heuristic on the mean blocks per row.
 int lanes_for(const bsr_s* A, int nrhs = 1);
+// The lane configuration for A's SpMV with or without symmetric reads (mir).
+int lanes_for_reads(const bsr_s* A, int nrhs, const int32_t* mir);
 // Time every compiled lane configuration of y = A x (vectors of dtype vdt, nrhs
 // columns) with device events and keep the fastest in A; returns its code.  Sync.
 int autotune_lanes(bsr_s* A, int vdt, int nrhs, hipStream_t s);

@@ -47,24 +47,42 @@ __device__ __forceinline__ void block_fma(const TM* __restrict__ b, const TA (&x
 // Lanes of a group stride over the blocks of the row; each lane takes U blocks per
 // step and issues all their loads before the multiply-adds, so a wave keeps
 // U * 64 blocks of loads in flight.
-template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA>
+//
+// SYM (square blocks, a structurally symmetric matrix): the strictly lower blocks
+// of the row are not read from their own position but as the transpose of their
+// mirror in the upper triangle, mir[k] = position of block (colidx[k], row).  Only
+// the upper triangle and the diagonal are then streamed from HBM; each mirrored
+// block was read by its own (earlier) row shortly before, so its second read is
+// mostly served by the caches.  For a symmetric matrix the products are the same,
+// in the same order within a lane.
+template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA, bool SYM = false>
 __device__ __forceinline__ void row_product(const int32_t* __restrict__ colidx,
                                             const TM* __restrict__ val, const TX* __restrict__ x,
-                                            int k0, int k1, int lane, TA (&acc)[BR * NR]) {
+                                            int k0, int k1, int lane, TA (&acc)[BR * NR], int row = 0,
+                                            const int32_t* __restrict__ mir = nullptr) {
+  static_assert(!SYM || BR == BC, "symmetric reads need square blocks");
 #pragma unroll
   for (int t = 0; t < BR * NR; ++t) acc[t] = TA(0);
   for (int kb = k0 + lane; kb < k1; kb += G * U) {
     TM bv[U][BR * BC];
     TA xv[U][BC * NR];
+    bool low[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = kb + u * G;
+      low[u] = false;
       if (k < k1) {
+        // with symmetric reads the block's source position comes from the mirror index
+        // (k itself for the diagonal and upper blocks), loaded alongside the column
+        // index, so the value load waits for one index load as in the full reads
         const int c = colidx[k];
+        int src = k;
+        if constexpr (SYM) src = mir[k];
         const TX* xc = x + static_cast<size_t>(c) * (BC * NR);
 #pragma unroll
         for (int t = 0; t < BC * NR; ++t) xv[u][t] = ld<TA>(xc + t);
-        const TM* b = val + static_cast<size_t>(k) * (BR * BC);
+        if constexpr (SYM) low[u] = c < row;
+        const TM* b = val + static_cast<size_t>(src) * (BR * BC);
 #pragma unroll
         for (int t = 0; t < BR * BC; ++t) bv[u][t] = b[t];
       } else {
@@ -72,6 +90,20 @@ __device__ __forceinline__ void row_product(const int32_t* __restrict__ colidx,
         for (int t = 0; t < BC * NR; ++t) xv[u][t] = TA(0);
 #pragma unroll
         for (int t = 0; t < BR * BC; ++t) bv[u][t] = TM{};
+      }
+    }
+    if constexpr (SYM) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+#pragma unroll
+          for (int j = i + 1; j < BC; ++j) {
+            const TM a = bv[u][i * BC + j], b = bv[u][j * BC + i];
+            bv[u][i * BC + j] = low[u] ? b : a;
+            bv[u][j * BC + i] = low[u] ? a : b;
+          }
+        }
       }
     }
 #pragma unroll
@@ -86,13 +118,15 @@ __device__ __forceinline__ void row_product(const int32_t* __restrict__ colidx,
 // each XCD has its own L2), so neighbouring rows, which gather the same x entries,
 // run on the same XCD at the same time.  A reducing epilogue (dot products) leaves
 // one partial sum per workgroup; every thread reaches that block reduction.
-template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA, class Epi>
+template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA, class Epi, bool SYM = false>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
                                                       const TM* __restrict__ val,
-                                                      const TX* __restrict__ x, Epi epi) {
+                                                      const TX* __restrict__ x, Epi epi,
+                                                      const int32_t* __restrict__ mir = nullptr,
+                                                      int chunk = kSpmvChunk) {
   constexpr int kRows = kBlock / G;
-  const int lb = xcd_chunked_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), kSpmvChunk);
+  const int lb = xcd_chunked_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), chunk);
   const int row = lb * kRows + static_cast<int>(threadIdx.x) / G;
   const int lane = static_cast<int>(threadIdx.x) % G;
   TA acc[BR * NR];
@@ -107,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nbr, const int32_t* __
   }
   const auto pre = epi.template prefetch<BR, NR, G>(active, row);
   if (active) {
-    row_product<BR, BC, NR, G, U, TM, TX, TA>(colidx, val, x, k0, k1, lane, acc);
+    row_product<BR, BC, NR, G, U, TM, TX, TA, SYM>(colidx, val, x, k0, k1, lane, acc, row, mir);
   } else {
 #pragma unroll
     for (int z = 0; z < BR * NR; ++z) acc[z] = TA(0);
@@ -215,13 +249,27 @@ __global__ __launch_bounds__(kBlock) void spmm8_kernel(int nbr, const int32_t* _
   epi.template apply8<BR, G>(active, row, lane, acc);
 }
 
+// mir != nullptr selects the symmetric reads (one right-hand side, square blocks;
+// ignored otherwise).  Their workgroup runs per XCD then span sym_dist / 8 rows (one
+// eighth of the matrix's typical lower bandwidth, e.g. one node plane of a 3D mesh in
+// natural order): run r + 8, the next run of the same XCD, holds the rows sym_dist
+// further on, whose mirrored lower blocks run r has just streamed into that XCD's L2.
 template <int BR, int BC, int NR, int G, int U, class TM, class TX, class TA, class Epi>
 int launch_g(int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val, const TX* x, const Epi& epi,
-             hipStream_t s) {
+             hipStream_t s, const int32_t* mir, int sym_dist) {
   const int grid = ceil_div(nbr, kBlock / G);
+  constexpr int kRows = kBlock / G;
+  const int sym_chunk =
+      sym_dist > 0 ? std::max(1, std::min(1 << 16, (sym_dist + kNumXcd * kRows / 2) / (kNumXcd * kRows))) : kSpmvChunk;
   if constexpr (NR == 8) {
     static_assert(!Epi::kReduce, "reducing epilogues take one right-hand side");
     spmm8_kernel<BR, BC, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
+  } else if constexpr (BR == BC) {
+    if (mir)
+      spmv_kernel<BR, BC, NR, G, U, TM, TX, TA, Epi, true><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi,
+                                                                                    mir, sym_chunk);
+    else
+      spmv_kernel<BR, BC, NR, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
   } else {
     spmv_kernel<BR, BC, NR, G, U, TM, TX, TA, Epi><<<grid, kBlock, 0, s>>>(nbr, rowptr, colidx, val, x, epi);
   }
@@ -239,13 +287,13 @@ constexpr int kLaneCodes[] = {8 * 8 + 1, 8 * 8 + 2, 16 * 8 + 1, 16 * 8 + 2, 32 *
 // workgroups (= number of partial sums written by a reducing epilogue).
 template <int BR, int BC, int NR, class TM, class TX, class TA, class Epi>
 int launch_rows(int code, int nbr, const int32_t* rowptr, const int32_t* colidx, const TM* val, const TX* x,
-                const Epi& epi, hipStream_t s) {
+                const Epi& epi, hipStream_t s, const int32_t* mir = nullptr, int sym_dist = 0) {
   if (nbr <= 0) return 0;
   int grid;
   switch (code) {
 #define BLK_CASE(GG, UU)                                                                                        \
   case GG * 8 + UU:                                                                                             \
-    grid = launch_g<BR, BC, NR, GG, UU, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s);                  \
+    grid = launch_g<BR, BC, NR, GG, UU, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s, mir, sym_dist);   \
     break;
     BLK_CASE(8, 1)
     BLK_CASE(8, 2)
@@ -257,7 +305,7 @@ int launch_rows(int code, int nbr, const int32_t* rowptr, const int32_t* colidx,
     BLK_CASE(64, 2)
 #undef BLK_CASE
     default:
-      grid = launch_g<BR, BC, NR, 64, 2, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s);
+      grid = launch_g<BR, BC, NR, 64, 2, TM, TX, TA, Epi>(nbr, rowptr, colidx, val, x, epi, s, mir, sym_dist);
       break;
   }
   HIP_CHECK(hipGetLastError());

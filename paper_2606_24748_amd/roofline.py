@@ -31,6 +31,15 @@ def spmv_bytes(nbr: int, nbc: int, br: int, bc: int, nnzb: int, val_size: int, v
     return b
 
 
+def spmv_sym_bytes(nbr: int, bs: int, n_upper: int, n_lower: int, val_size: int, vec_size: int) -> int:
+    """Symmetric reads of a square-blocked symmetric A (bsr_spmv_sym): the diagonal and
+    upper blocks once (values + column index), a column index and a mirror index per
+    strictly lower block (its values are the transposed mirror, already read), row
+    pointers, x once and y once."""
+    b = n_upper * block_bytes(bs, bs, val_size) + n_lower * 2 * IDX + IDX * (nbr + 1)
+    return b + vec_size * 2 * nbr * bs
+
+
 def spmv_flops(nnzb: int, br: int, bc: int, nrhs: int = 1) -> int:
     return 2 * nnzb * br * bc * nrhs
 

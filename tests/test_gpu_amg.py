@@ -149,3 +149,33 @@ def test_f32_hierarchy_lambdas_and_recompute(n):
     B.vcycle_apply(M, dev(r), z)
     zo = solve.vcycle(H2, r)
     assert rel2(z.cpu().numpy(), zo) <= 1e-4
+
+
+@pytest.mark.parametrize("hier", [B.F64, B.F32])
+def test_symmetric_reads_give_identical_vcycle_and_pcg(hier):
+    """The hierarchy's symmetric reads (sym_spmv = 1, the default; FP64 operators) against
+    full reads (sym_spmv = 0): every level operator is symmetric bit for bit, so the two
+    differ only in the grouping of the row sums: lambda_hat and the V-cycle agree to
+    roundoff, CG takes the same iterations to the same solution."""
+    print(f"symmetric reads hier={hier}", flush=True)
+    m, i, j, v, A = q1_problem(14, mat_seed=5)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    out = []
+    for sym in (0, 1):
+        o = B.blkamg_opts_default()
+        o.hier_dtype, o.p_dtype, o.sym_spmv = hier, hier, sym
+        M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+        B.amg_smoother_refresh(M)
+        r = dev(np.random.default_rng(9).uniform(-1, 1, m.n_dof))
+        z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+        B.vcycle_apply(M, r, z)
+        b = dev(synth.rhs(m, 4))
+        x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+        code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+        assert code == B.OK
+        out.append((M.lambdas().copy(), z.cpu(), x.cpu(), it))
+    tol = 1e-12 if hier == B.F64 else 0.0  # FP32 hierarchies read every block either way
+    assert np.all(np.abs(out[0][0] - out[1][0]) <= tol * out[0][0])
+    assert rel2(out[1][1].numpy(), out[0][1].numpy()) <= max(tol, 1e-14 if hier == B.F64 else 1e-9)
+    assert rel2(out[1][2].numpy(), out[0][2].numpy()) <= 1e-9 and out[0][3] == out[1][3]

@@ -284,3 +284,53 @@ def test_ptap_lane_mappings_agree(bs, monkeypatch):
                 ref = got.val.copy()
             else:
                 assert np.array_equal(got.val, ref), tune
+
+
+@pytest.mark.parametrize("bs", [3, 6])
+def test_spmv_sym_is_the_symmetric_completion(bs):
+    """bsr_spmv_sym applies S (A's diagonal and upper blocks, lower blocks as transposed
+    mirrors): against the oracle's S on a symmetric pattern with unrelated values, and
+    equal to bsr_spmv on a symmetric matrix up to the grouping of the row sums (the
+    symmetric reads use their own lane shape), F64 and F32."""
+    print(f"spmv_sym bs={bs}", flush=True)
+    rp, ci, v = synth.random_spd_bsr(2311, bs, seed=bs, max_per_row=9)
+    A = S.Bsr(2311, 2311, bs, bs, rp.astype(np.int64), ci.astype(np.int64), v)
+    W = A.with_values(np.random.default_rng(bs).uniform(-1, 1, A.val.shape))
+    x = np.random.default_rng(2).uniform(-1, 1, A.nbr * bs)
+    y0 = np.random.default_rng(3).uniform(-1, 1, A.nbr * bs)
+    HW, _ = to_device_bsr(W)
+    y = dev(y0)
+    B.bsr_spmv_sym(HW, 0.5, dev(x), -2.0, y)
+    assert rel2(y.cpu().numpy(), S.spmv(S.symmetric_completion(W), x, 0.5, -2.0, y0)) <= 1e-13
+    for dt, tdt in ((B.F64, torch.float64), (B.F32, torch.float32)):
+        HA, _ = to_device_bsr(A, dt)
+        xs = dev(x, tdt)
+        y1 = torch.zeros(A.nbr * bs, dtype=tdt, device="cuda")
+        y2 = torch.zeros_like(y1)
+        B.bsr_spmv(HA, 1.0, xs, 0.0, y1)
+        B.bsr_spmv_sym(HA, 1.0, xs, 0.0, y2)
+        assert rel2(y2.double().cpu().numpy(), y1.double().cpu().numpy()) <= (1e-15 if dt == B.F64 else 1e-7), dt
+
+
+def test_spmv_sym_on_the_elasticity_operator_and_refusals():
+    """The assembled Q1 operator is symmetric bit for bit, so the symmetric reads apply A
+    itself (equal to the full reads up to the grouping of the row sums, against the
+    oracle at 1e-14); rectangular blocks and unsymmetric patterns are refused."""
+    m, i, j, v, A = q1_problem(14, mat_seed=3)
+    HA, _ = to_device_bsr(A)
+    x = dev(np.random.default_rng(7).uniform(-1, 1, A.nbr * 3))
+    y1 = torch.zeros(A.nbr * 3, dtype=torch.float64, device="cuda")
+    y2 = torch.zeros_like(y1)
+    B.bsr_spmv(HA, 1.0, x, 0.0, y1)
+    B.bsr_spmv_sym(HA, 1.0, x, 0.0, y2)
+    assert rel2(y2.cpu().numpy(), y1.cpu().numpy()) <= 1e-15
+    assert rel2(y2.cpu().numpy(), S.spmv(A, x.cpu().numpy())) <= 1e-14
+    R = _rand(40, 30, 3, 6, seed=1)
+    HR, _ = to_device_bsr(R)
+    with pytest.raises(B.BlkAmgError) as e:
+        B.bsr_spmv_sym(HR, 1.0, dev(np.zeros(180)), 0.0, torch.zeros(120, dtype=torch.float64, device="cuda"))
+    assert e.value.code == B.EINVAL
+    U = S.Bsr(3, 3, 3, 3, np.array([0, 1, 3, 4]), np.array([0, 0, 1, 2]), np.ones((4, 3, 3)))
+    HU, _ = to_device_bsr(U)
+    with pytest.raises(B.BlkAmgError):
+        B.bsr_spmv_sym(HU, 1.0, dev(np.zeros(9)), 0.0, torch.zeros(9, dtype=torch.float64, device="cuda"))

@@ -190,3 +190,33 @@ def test_ptap_tiny_mesh_brute_force_and_symmetry():
         got = _dense_loops(H.levels[lev + 1].A)
         assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
         assert np.linalg.norm(got - got.T) <= 1e-14 * np.linalg.norm(got)
+
+
+def test_symmetric_completion_pins():
+    """S keeps the diagonal and upper blocks, its strictly lower part is the transpose of
+    the upper part (so dense(S) - dense(S)^T vanishes outside the diagonal blocks), and
+    S = A for a symmetric matrix; a pattern without mirrors is refused."""
+    rp, ci, v = synth.random_spd_bsr(40, 3, seed=3, max_per_row=5)
+    A = S.Bsr(40, 40, 3, 3, rp.astype(np.int64), ci.astype(np.int64), v)
+    assert np.array_equal(S.symmetric_completion(A).val, A.val)
+    # the same pattern with unrelated values
+    W = A.with_values(np.random.default_rng(4).uniform(-1, 1, A.val.shape))
+    Sw = S.symmetric_completion(W)
+    rows = np.repeat(np.arange(W.nbr), np.diff(W.rowptr))
+    up = W.colidx >= rows
+    assert np.array_equal(Sw.val[up], W.val[up]) and not np.array_equal(Sw.val[~up], W.val[~up])
+    D = S.to_dense(Sw)
+    E = D - D.T
+    for r in range(W.nbr):
+        E[3 * r:3 * r + 3, 3 * r:3 * r + 3] = 0.0
+    assert np.abs(E).max() == 0.0
+    # x^T S y = y^T S x up to the diagonal blocks' asymmetry
+    Dg = np.zeros_like(D)
+    for r in range(W.nbr):
+        Dg[3 * r:3 * r + 3, 3 * r:3 * r + 3] = D[3 * r:3 * r + 3, 3 * r:3 * r + 3]
+    x, y = np.random.default_rng(5).uniform(-1, 1, (2, 120))
+    assert abs(x @ S.spmv(Sw, y) - y @ S.spmv(Sw, x) - (x @ Dg @ y - y @ Dg @ x)) <= 1e-12
+    # a lower block without its mirror
+    bad = S.Bsr(2, 2, 1, 1, np.array([0, 1, 2]), np.array([0, 0]), np.ones((2, 1, 1)))
+    with pytest.raises(AssertionError):
+        S.symmetric_completion(bad)
