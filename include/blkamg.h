@@ -351,6 +351,18 @@ int sa_aggregate(int32_t nbr, const int32_t* h_rowptr, const int32_t* h_colidx,
  * Sync (one 4-byte read per round); allocates scratch. */
 int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg,
                         int32_t* n_agg, int32_t* n_rounds, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sa_aggregate_device with the same
+ * arguments and results, on a static 64 MiB scratch array per GPU (held by the library
+ * from the first call on a device until the process ends) instead of an allocation;
+ * no hipMalloc, hipFree or allocating library routine is called.  Graphs whose scratch
+ * exceeds 64 MiB (30 bytes per vertex plus a scan temporary: about 2.2 million
+ * vertices) are refused with EINVAL before any launch.  Every call on one GPU shares
+ * that GPU's scratch, so calls that overlap on one GPU (other threads, other streams)
+ * race; each call initialises every scratch value it reads.  Sync, as
+ * sa_aggregate_device. */
+int sa_aggregate_device_noalloc(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg,
+                                int32_t* n_agg, int32_t* n_rounds, void* stream);
 /* Tentative prolongator on the device (paper §2.2; the device-resident setup of §6):
  * per aggregate, the near-null-space rows of its members in ascending node order,
  * B_g = Q_g R_g by a thin Householder QR with diag(R_g) > 0; the members' rows of P~

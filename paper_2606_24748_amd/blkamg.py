@@ -88,6 +88,7 @@ _SIG = {
     "coo_plan_map": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_i64), C.POINTER(_i64)]),
     "coo_assemble_blocked": (C.c_int, [_p, _p, C.c_int, C.c_int, _p, _p]),
     "sa_aggregate_device": (C.c_int, [_p, _p, C.c_uint64, _p, _pi32, _pi32, _p]),
+    "sa_aggregate_device_noalloc": (C.c_int, [_p, _p, C.c_uint64, _p, _pi32, _pi32, _p]),
     "fe_q1_stream": (C.c_int, [_i64, _p, _p, _p, _p, _i64, _p, _p]),
     "fe_ebe_plan_create": (C.c_int, [_p, _i64, _p, _p, C.POINTER(_p)]),
     "fe_ebe_plan_info": (C.c_int, [_p, _pi32, C.POINTER(_i64)]),
@@ -409,6 +410,23 @@ def sa_aggregate_device(A: Bsr, dirichlet=None, seed=LUBY_SEED, stream=None):
     _check(_lib.sa_aggregate_device(A.h, _ptr(d), seed, _ptr(agg), C.byref(na), C.byref(nr), _stream(stream)),
            "sa_aggregate_device")
     return agg, na.value, nr.value
+
+
+def sa_aggregate_device_noalloc(A: Bsr, d_dirichlet, d_agg, seed=LUBY_SEED, stream=None):
+    """sa_aggregate_device on the library's static scratch, writing into caller tensors:
+    d_dirichlet (device uint8 [nbr] or None) and d_agg (device int32 [nbr]).  Allocates
+    nothing on the device.  Returns (n_agg, rounds)."""
+    n = A.info()["nbr"]
+    if not (hasattr(d_agg, "is_cuda") and d_agg.is_cuda and d_agg.is_contiguous() and d_agg.numel() == n
+            and str(d_agg.dtype) == "torch.int32"):
+        raise ValueError("d_agg must be a contiguous device int32 tensor with one entry per block row")
+    if d_dirichlet is not None and not (d_dirichlet.is_cuda and d_dirichlet.is_contiguous()
+                                        and d_dirichlet.numel() == n and str(d_dirichlet.dtype) == "torch.uint8"):
+        raise ValueError("d_dirichlet must be a contiguous device uint8 tensor with one flag per block row")
+    na, nr = _i32(), _i32()
+    _check(_lib.sa_aggregate_device_noalloc(A.h, _ptr(d_dirichlet), seed, _ptr(d_agg), C.byref(na), C.byref(nr),
+                                            _stream(stream)), "sa_aggregate_device_noalloc")
+    return na.value, nr.value
 
 
 def sa_tentative_device(agg, n_agg, B_null, stream=None):

@@ -17,6 +17,7 @@
 // three apart, so that root is unique) and the remaining vertices join the
 // neighbouring aggregate holding most of their neighbours, ties to the smallest id.
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include <hipcub/hipcub.hpp>
@@ -328,12 +329,57 @@ void mis_aggregate(const bsr_s* A, const uint8_t* d_dirichlet, uint64_t seed, in
   if (n_rounds) *n_rounds = rounds;
 }
 
+// Static scratch of the allocation-free entry point: one array per GPU, loaded with
+// the library's code object and held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for the
+// device symbol): it uses the device address that hipGetSymbolAddress returns for
+// the current device, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+char* scratch_on_current_device() {
+  int dev = -1;
+  HIP_CHECK(hipGetDevice(&dev));
+  BLK_REQUIRE(dev >= 0 && dev < kMaxDevices, BLKAMG_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    BLK_REQUIRE(p != nullptr, BLKAMG_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace blk
 
 using namespace blk;
 
 extern "C" {
+
+int sa_aggregate_device_noalloc(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg, int32_t* n_agg,
+                                int32_t* n_rounds, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(A != nullptr && n_agg != nullptr, BLKAMG_EINVAL, "NULL argument");
+  BLK_REQUIRE(A->nbr == A->nbc, BLKAMG_EINVAL, "A must be square");
+  BLK_REQUIRE(A->nbr == 0 || d_agg != nullptr, BLKAMG_EINVAL, "d_agg is NULL");
+  *n_agg = 0;
+  if (n_rounds) *n_rounds = 0;
+  if (A->nbr == 0) return BLKAMG_OK;
+  hipStream_t s = as_stream(stream);
+  const MisScratch L = mis_scratch_layout(A->nbr, s);
+  BLK_REQUIRE(L.total <= kNoAllocScratchBytes, BLKAMG_EINVAL,
+              "graph too large for the static scratch: " + std::to_string(A->nbr) + " vertices need " +
+                  std::to_string(L.total) + " bytes, the limit is " + std::to_string(kNoAllocScratchBytes) +
+                  " (about 2.2 million vertices); use sa_aggregate_device");
+  mis_aggregate(A, d_dirichlet, seed, d_agg, n_agg, n_rounds, scratch_on_current_device(), L, s);
+  BLK_API_END
+}
 
 int sa_aggregate_device(bsr_t A, const uint8_t* d_dirichlet, uint64_t seed, int32_t* d_agg, int32_t* n_agg,
                         int32_t* n_rounds, void* stream) {
