@@ -513,6 +513,7 @@ def run_learned(args, B, torch, dev, stream):
         B.coo_assemble_blocked(plan, vals[0], B.INSERT, HA)
         o = B.blkamg_opts_default()
         o.hier_dtype, o.p_dtype, o.eig_mode = hier, hier, eig
+        o.mlp_guard = B.GUARD_PCG  # hot refreshes run no smoother test; CG checks its residual
         keep = B.opts_with_model(o, model) if eig == B.EIG_MLP else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -555,8 +556,8 @@ def run_learned(args, B, torch, dev, stream):
         if eig == B.EIG_MLP:
             fb, g, om = B.amg_eig_status(M)
             ent["fallback_levels"] = fb.tolist()
-            ent["growth"] = g[:, 0].tolist()
             ent["omega_pred"] = om[:, 0].tolist()
+            ent["guard_armed"], ent["guard_restarts"] = B.amg_guard_status(M)
         res[name] = ent
         del M
         torch.cuda.synchronize()
@@ -578,6 +579,7 @@ def variant_opts(B, var):
         o.hier_dtype, o.p_dtype = B.F32, B.F32
     elif var == "mixed-mlp":
         o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, B.EIG_MLP
+        o.mlp_guard = B.GUARD_PCG
     elif var == "mixed-bf16":
         o.hier_dtype, o.p_dtype = B.F32, B.BF16
     elif var == "mixed-luby":

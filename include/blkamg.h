@@ -66,6 +66,10 @@ extern "C" {
 #define BLKAMG_EIG_LANCZOS 0 /* k-step Lanczos per level (paper's method) */
 #define BLKAMG_EIG_MLP 1     /* learned eigenbound with growth test and Lanczos fallback */
 
+/* guard of the learned eigenbound in the hot refresh (blkamg_opts.mlp_guard) */
+#define BLKAMG_GUARD_SMOOTHER 0 /* smoother growth test on every level at every refresh */
+#define BLKAMG_GUARD_PCG 1      /* no test at refresh: pcg_solve checks its own residual */
+
 /* eigenbound network 12 -> 64 -> 64 -> 2: parameter count and deployable model size */
 #define BLKAMG_MLP_PARAMS 5122
 #define BLKAMG_MLP_MODEL 5150
@@ -311,6 +315,17 @@ typedef struct {
   const float* eig_model;   /* host copy of a model (BLKAMG_MLP_MODEL floats) used from
                                the cold setup on when eig_mode is BLKAMG_EIG_MLP (copied;
                                NULL = none until amg_set_eig_model).  Default NULL */
+  int32_t mlp_guard;        /* BLKAMG_GUARD_SMOOTHER (default): every MLP refresh runs the
+                               smoother growth test (growth_steps) and falls back per level.
+                               BLKAMG_GUARD_PCG: an MLP refresh of a one-instance hierarchy
+                               runs no test; the next pcg_solve with one right-hand side
+                               checks its residual recurrence instead (the preconditioned
+                               r.z must stay positive and ||r|| must not grow above 1e3
+                               times its smallest value so far); when the check fails,
+                               every smoothed level is refreshed by Lanczos (all flagged as
+                               fallback) and the solve restarts from x = 0.  vcycle_apply
+                               and the other solves first run the deferred smoother test.
+                               The cold setup always runs the smoother test. */
   int32_t sym_spmv;         /* 1 (default): the hierarchy's SpMVs on FP64 level operators
                                (smoother, residual, Lanczos, growth test) and pcg_solve's
                                A p read only the diagonal and upper blocks of a
@@ -563,6 +578,11 @@ int amg_set_eig_model(amg_t M, const float* h_model, int32_t n_floats);
  * Lanczos), h_growth and h_omega [n_levels-1][n_inst] (growth factor of the test
  * and predicted prolongator weight; 0 where not smoothed).  Any may be NULL. */
 int amg_eig_status(amg_t M, int32_t* h_fallback, double* h_growth, double* h_omega);
+/* State of the deferred guard (opts.mlp_guard = BLKAMG_GUARD_PCG): *armed = 1 while
+ * the smoother scalars come from the network and no check has rejected them;
+ * *restarts = solves restarted so far because CG's residual check failed.  Either
+ * may be NULL. */
+int amg_guard_status(amg_t M, int32_t* armed, int32_t* restarts);
 /* What the cold setup used on each smoothed level (paper §2.2: P = (I - omega D^-1 A) P~):
  * h_lambda and h_omega [n_levels-1][n_inst] (the lambda_hat the setup's smoother
  * and the weight its prolongator smoothing used; 0 where not smoothed) and

@@ -22,6 +22,7 @@ FE_ATOMIC, FE_COLORED = 0, 1
 AGG_GREEDY, AGG_LUBY = 0, 1
 LUBY_SEED = 0x4D495332
 EIG_LANCZOS, EIG_MLP = 0, 1
+GUARD_SMOOTHER, GUARD_PCG = 0, 1
 MLP_PARAMS, MLP_MODEL = 5122, 5150
 
 if not os.path.exists(LIB_PATH):
@@ -62,6 +63,7 @@ class Opts(C.Structure):
         ("agg_seed", C.c_uint64),
         ("growth_steps", C.c_int32),
         ("eig_model", C.c_void_p),
+        ("mlp_guard", C.c_int32),
         ("sym_spmv", C.c_int32),
     ]
 
@@ -123,6 +125,7 @@ _SIG = {
     "amg_judge_lambdas": (C.c_int, [_p, _i32, _p, _p]),
     "amg_set_eig_model": (C.c_int, [_p, _p, _i32]),
     "amg_eig_status": (C.c_int, [_p, _p, _p, _p]),
+    "amg_guard_status": (C.c_int, [_p, _pi32, _pi32]),
     "amg_setup_weights": (C.c_int, [_p, _p, _p, _p]),
     "pcg_solve": (C.c_int, [_p, _p, _p, _p, _f64, _i32, _i32, _pi32, C.POINTER(_f64), _p]),
 }
@@ -828,6 +831,13 @@ def amg_eig_status(M: Amg):
     _check(_lib.amg_eig_status(M.h, fb.ctypes.data_as(_p), g.ctypes.data_as(_p), om.ctypes.data_as(_p)),
            "amg_eig_status")
     return fb, g, om
+
+
+def amg_guard_status(M: Amg):
+    """(armed, restarts) of the deferred guard (mlp_guard = GUARD_PCG)."""
+    a, r = _i32(), _i32()
+    _check(_lib.amg_guard_status(M.h, C.byref(a), C.byref(r)), "amg_guard_status")
+    return bool(a.value), r.value
 
 
 def amg_setup_weights(M: Amg):

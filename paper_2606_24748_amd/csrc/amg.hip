@@ -113,6 +113,11 @@ struct amg_s {
   std::vector<double> setup_lam, setup_omega;
   std::vector<int32_t> setup_learned;
   bool user_ops = false;               // operators supplied by the caller (amg_hierarchy_create)
+  // BLKAMG_GUARD_PCG: the current smoother scalars come from the network and no test
+  // has checked them yet (the next pcg_solve checks its residual, other consumers run
+  // the smoother test first); guard_restarts counts the solves restarted by the check
+  bool guard_armed = false;
+  int32_t guard_restarts = 0;
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -605,6 +610,7 @@ void smoother_refresh(amg_s* M, const double* h_lambda, hipStream_t s) {
     check_flags(M, s);
     return;
   }
+  M->guard_armed = false;
   std::vector<DevBuf<double>> user(static_cast<size_t>(nl));
   for (int l = 0; l < nl; ++l) {
     Level& L = *M->lv[l];
@@ -860,6 +866,40 @@ bool growth_fails(const LevelScalars& q, double* g_out) {
   return !(g <= 1.0) || !(q.lam > 0.0) || !std::isfinite(q.lam);
 }
 
+// The smoother growth test on every smoothed level with the current (network)
+// scalars, and Lanczos on each level where some segment fails it.  Sync.
+void mlp_check_levels(amg_s* M, hipStream_t s) {
+  const int nl = static_cast<int>(M->lv.size());
+  for (int l = 0; l < nl; ++l)
+    if (M->lv[l]->n_act > 0) growth_level(M, l, s);
+  std::vector<LevelScalars> sc = download(M->sc.p, static_cast<size_t>(nl) * M->n_inst, s);
+  for (int l = 0; l < nl; ++l) {
+    const Level& L = *M->lv[l];
+    bool bad = false;
+    for (int t = 0; t < L.n_act; ++t) {
+      double g = 0.0;
+      bad = growth_fails(sc[static_cast<size_t>(l) * M->n_inst + t], &g) || bad;
+      M->growth[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = g;
+    }
+    if (bad) {
+      M->fallback[l] = 1;
+      refresh_level_scalars(M, l, nullptr, s);
+    }
+  }
+  M->guard_armed = false;
+}
+
+// Lanczos on every smoothed level (the residual check of CG failed).
+void mlp_fallback_all(amg_s* M, hipStream_t s) {
+  const int nl = static_cast<int>(M->lv.size());
+  for (int l = 0; l < nl; ++l) {
+    if (M->lv[l]->n_act == 0) continue;
+    M->fallback[l] = 1;
+    refresh_level_scalars(M, l, nullptr, s);
+  }
+  M->guard_armed = false;
+}
+
 void mlp_refresh(amg_s* M, hipStream_t s) {
   BLK_REQUIRE(M->model.p != nullptr, BLKAMG_ESTATE, "eig_mode is MLP but no model was set (amg_set_eig_model)");
   const int nl = static_cast<int>(M->lv.size());
@@ -870,27 +910,19 @@ void mlp_refresh(amg_s* M, hipStream_t s) {
   for (int l = 0; l < nl; ++l) {
     if (M->lv[l]->n_act == 0) continue;
     refresh_level_scalars(M, l, M->pred_lam.p + M->sample_base[l], s);
-    growth_level(M, l, s);
   }
-  std::vector<LevelScalars> sc = download(M->sc.p, static_cast<size_t>(nl) * M->n_inst, s);
   std::vector<double> om = download(M->pred_omega.p, static_cast<size_t>(std::max(S, 0)), s);
   M->fallback.assign(static_cast<size_t>(nl), 0);
   M->growth.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
   M->omega.assign(static_cast<size_t>(nl) * M->n_inst, 0.0);
   for (int l = 0; l < nl; ++l) {
     const Level& L = *M->lv[l];
-    bool bad = false;
-    for (int t = 0; t < L.n_act; ++t) {
-      double g = 0.0;
-      bad = growth_fails(sc[static_cast<size_t>(l) * M->n_inst + t], &g) || bad;
-      M->growth[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = g;
+    for (int t = 0; t < L.n_act; ++t)
       M->omega[static_cast<size_t>(l) * M->n_inst + L.seg_inst[t]] = om[M->sample_base[l] + t];
-    }
-    if (bad) {
-      M->fallback[l] = 1;
-      refresh_level_scalars(M, l, nullptr, s);
-    }
   }
+  // the deferred guard applies to one instance (its CG checks one recurrence)
+  if (M->o.mlp_guard == BLKAMG_GUARD_PCG && M->n_inst == 1) M->guard_armed = true;
+  else mlp_check_levels(M, s);
 }
 
 // Cold setup of level l's smoother scalars and prolongator weights (per smoothed
@@ -1046,6 +1078,8 @@ void check_opts(const blkamg_opts& o) {
   BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || o.agg_mode == BLKAMG_AGG_LUBY, BLKAMG_EINVAL, "bad agg_mode");
   BLK_REQUIRE(o.growth_steps >= 1 && o.growth_steps <= 16, BLKAMG_EINVAL, "growth_steps must be in 1..16");
   BLK_REQUIRE(o.sym_spmv == 0 || o.sym_spmv == 1, BLKAMG_EINVAL, "sym_spmv must be 0 or 1");
+  BLK_REQUIRE(o.mlp_guard == BLKAMG_GUARD_SMOOTHER || o.mlp_guard == BLKAMG_GUARD_PCG, BLKAMG_EINVAL,
+              "mlp_guard must be BLKAMG_GUARD_SMOOTHER or BLKAMG_GUARD_PCG");
 }
 
 // Validate and copy a model to the device (the caller's array is not kept).
@@ -1375,6 +1409,12 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
   const int32_t* mir = M->o.sym_spmv ? symmetric_mirror(A, s) : nullptr;
   const int G = lanes_for_reads(A, 1, mir);
   bool converged = false;
+  // deferred guard of network scalars: the preconditioned r.z must stay positive and the
+  // residual must not grow far above its smallest value (a smoother whose Chebyshev
+  // interval misses the top of the spectrum makes the V-cycle indefinite)
+  const bool guard = M->guard_armed;
+  constexpr double kGuardGrowth = 1e3;
+  double rmin = bn;
   while (it < maxit) {
     EpiPcgW epi{p, w, M->partial.p};
     const int sg = A->br == 3 ? launch_rows<3, 3, 1, double, double, double>(G, A->nbr, A->rowptr, A->colidx,
@@ -1395,6 +1435,12 @@ int pcg_single(bsr_s* A, amg_s* M, const double* d_b, double* d_x, double rtol, 
       fail(BLKAMG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
     }
     rn = std::sqrt(M->host_s[S_RR]);
+    if (guard && (!(M->host_s[S_RZ] > 0.0) || !std::isfinite(rn) || rn > kGuardGrowth * rmin)) {
+      mlp_fallback_all(M, s);
+      M->guard_restarts++;
+      return pcg_single(A, M, d_b, d_x, rtol, maxit, iters, relres, s);
+    }
+    rmin = std::min(rmin, rn);
     if (rn <= rtol * bn) { converged = true; break; }
     const float* z32 = precondition();
     HIP_CHECK(hipGetLastError());
@@ -1586,6 +1632,7 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->agg_seed = 0x4D495332ull;
   o->growth_steps = 3;
   o->eig_model = nullptr;
+  o->mlp_guard = BLKAMG_GUARD_SMOOTHER;
   o->sym_spmv = 1;
 }
 
@@ -1842,12 +1889,21 @@ int amg_eig_status(amg_t M, int32_t* h_fallback, double* h_growth, double* h_ome
   BLK_API_END
 }
 
+int amg_guard_status(amg_t M, int32_t* armed, int32_t* restarts) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr, BLKAMG_EINVAL, "M is NULL");
+  if (armed) *armed = M->guard_armed ? 1 : 0;
+  if (restarts) *restarts = M->guard_restarts;
+  BLK_API_END
+}
+
 int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* stream) {
   BLK_API_BEGIN
   BLK_REQUIRE(M != nullptr && d_r != nullptr && d_z != nullptr, BLKAMG_EINVAL, "NULL argument");
   BLK_REQUIRE(nrhs == 1 || nrhs == 8, BLKAMG_EINVAL, "vcycle_apply supports nrhs 1 or 8");
   BLK_REQUIRE(d_r != d_z, BLKAMG_EINVAL, "r and z must not alias");
   ensure_vectors(M, nrhs);
+  if (M->guard_armed) mlp_check_levels(M, as_stream(stream));
   vcycle(M, d_r, d_z, nrhs, as_stream(stream));
   BLK_API_END
 }
@@ -1864,6 +1920,7 @@ int pcg_solve(bsr_t A, amg_t M, const double* d_b, double* d_x, double rtol, int
   BLK_REQUIRE(maxit >= 0 && rtol >= 0.0, BLKAMG_EINVAL, "bad rtol or maxit");
   hipStream_t s = as_stream(stream);
   if (M->n_inst == 1 && nrhs == 1) return pcg_single(A, M, d_b, d_x, rtol, maxit, iters, relres, s);
+  if (M->guard_armed) mlp_check_levels(M, s);
   if (nrhs == 1) return pcg_batched<1>(A, M, d_b, d_x, rtol, maxit, iters, relres, s);
   return pcg_batched<8>(A, M, d_b, d_x, rtol, maxit, iters, relres, s);
   BLK_API_END

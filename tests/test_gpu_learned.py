@@ -1,8 +1,10 @@
 """Ablation of the trained eigenbound network on a problem outside its training set
 (32^3 elements, material seed 21; training used seeds 1000+): the same FP32
-hierarchy refreshed by Lanczos and by the network.  The network must keep the
-smoother valid (no fallback, lambda within 15% of the 50-step reference on every
-level), keep PCG's iteration count within 2 of the Lanczos run, and refresh faster."""
+hierarchy refreshed by Lanczos and by the network (deferred guard: CG checks its own
+residual).  The network must keep the smoother valid one-sidedly (the Chebyshev
+interval's end 1.1 lambda_net covers the 50-step reference lambda_max on every level,
+no fallback, no restart), reach the same PCG iteration count as the Lanczos run, and
+make refresh + solve faster."""
 import numpy as np
 import pytest
 
@@ -44,7 +46,7 @@ def test_network_against_lanczos_ablation():
     out = {}
     for mode in (B.EIG_LANCZOS, B.EIG_MLP):
         o = B.blkamg_opts_default()
-        o.hier_dtype, o.p_dtype, o.eig_mode = B.F32, B.F32, mode
+        o.hier_dtype, o.p_dtype, o.eig_mode, o.mlp_guard = B.F32, B.F32, mode, B.GUARD_PCG
         M = B.amg_setup(HA, m.coords, m.dirichlet, o)
         if mode == B.EIG_MLP:
             B.amg_set_eig_model(M, train_eigmlp.load_model())
@@ -53,16 +55,28 @@ def test_network_against_lanczos_ablation():
         x = torch.zeros_like(b)
         code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
         assert code == B.OK and rel <= 1e-8
+        lam = M.lambdas().copy()
+        tot = []
+        for _ in range(5):  # refresh + solve, end to end
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            B.amg_smoother_refresh(M)
+            B.pcg_solve(HA, M, b, x, rtol=1e-8)
+            e1.record()
+            e1.synchronize()
+            tot.append(e0.elapsed_time(e1))
         judge = B.amg_judge_lambdas(M, 50)[:, 0]
-        out[mode] = dict(ms=ms, its=its, lam=M.lambdas().copy(), judge=judge)
+        out[mode] = dict(ms=ms, its=its, lam=lam, judge=judge, total=float(np.median(tot)))
         if mode == B.EIG_MLP:
-            fb, g, _ = B.amg_eig_status(M)
-            assert not fb.any() and np.all(g[:, 0] < 1.0)
+            fb, _, _ = B.amg_eig_status(M)
+            assert not fb.any() and B.amg_guard_status(M) == (True, 0)
     lz, nn = out[B.EIG_LANCZOS], out[B.EIG_MLP]
-    err_l = np.abs(lz["lam"] / lz["judge"] - 1)
-    err_n = np.abs(nn["lam"] / nn["judge"] - 1)
-    print(f"refresh ms lanczos {lz['ms']:.3f} network {nn['ms']:.3f}; its {lz['its']} vs {nn['its']}; "
-          f"lambda err lanczos {np.round(err_l, 4).tolist()} network {np.round(err_n, 4).tolist()}", flush=True)
-    assert np.all(err_n <= 0.15)
-    assert nn["its"] <= lz["its"] + 2
-    assert nn["ms"] < lz["ms"]
+    err_l = lz["lam"] / lz["judge"] - 1
+    nn_err = nn["lam"] / nn["judge"] - 1
+    print(f"refresh ms lanczos {lz['ms']:.3f} network {nn['ms']:.3f}; refresh + solve {lz['total']:.2f} vs "
+          f"{nn['total']:.2f} ms; its {lz['its']} vs {nn['its']}; lambda err lanczos {np.round(err_l, 4).tolist()} "
+          f"network {np.round(nn_err, 4).tolist()}", flush=True)
+    assert np.all(1.1 * nn["lam"] >= nn["judge"])  # one-sided: the interval covers lambda_max
+    assert np.all(np.abs(nn_err) <= 0.15)
+    assert nn["its"] == lz["its"]
+    assert nn["ms"] < lz["ms"] and nn["total"] < lz["total"]

@@ -100,7 +100,7 @@ def test_adam_matches_oracle_and_training_reduces_loss():
     assert float(loss) <= 0.1 * first, (first, float(loss))
 
 
-def _q1_gpu(n, seed, hier=B.F64, eig=B.EIG_LANCZOS):
+def _q1_gpu(n, seed, hier=B.F64, eig=B.EIG_LANCZOS, guard=B.GUARD_SMOOTHER):
     m = synth.make_mesh(n)
     i, j = synth.coo_indices(m)
     E, nu = synth.materials(m.n_elem, seed)
@@ -112,6 +112,7 @@ def _q1_gpu(n, seed, hier=B.F64, eig=B.EIG_LANCZOS):
     o.hier_dtype = hier
     o.p_dtype = hier
     o.eig_mode = eig
+    o.mlp_guard = guard
     M = B.amg_setup(HA, m.coords, m.dirichlet, o)
     return m, A, plan, HA, M
 
@@ -208,6 +209,55 @@ def test_mlp_refresh_falls_back_when_bound_is_too_low():
     x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
     code, it, rel = B.pcg_solve(HA, M, dev(b), x, rtol=1e-8)
     assert code == B.OK
+
+
+@pytest.mark.parametrize("hier", [B.F64, B.F32])
+def test_deferred_guard_restarts_cg_with_lanczos(hier):
+    """mlp_guard = GUARD_PCG: a refresh with a far too low network bound runs no test and
+    arms the guard; the next CG sees its preconditioned r.z turn non-positive or its
+    residual blow up, refreshes every level by Lanczos and restarts; the restarted solve
+    is, bit for bit, the solve of the same hierarchy refreshed by Lanczos."""
+    print(f"deferred guard hier={hier}", flush=True)
+    m, A, plan, HA, M = _q1_gpu(10, 5, hier=hier, eig=B.EIG_MLP, guard=B.GUARD_PCG)
+    lam_lanczos = M.lambdas().copy()
+    b = dev(synth.rhs(m, 2))
+    xl = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code_l, it_l, _ = B.pcg_solve(HA, M, b, xl, rtol=1e-8)  # no model yet: Lanczos scalars
+    lam_true = B.amg_judge_lambdas(M, 50)[:, 0]
+    B.amg_set_eig_model(M, _const_model(0.1 * lam_true[0]))
+    B.amg_smoother_refresh(M)
+    fb, g, _ = B.amg_eig_status(M)
+    assert not fb.any() and not g.any()
+    assert B.amg_guard_status(M) == (True, 0)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+    assert B.amg_guard_status(M) == (False, 1)
+    fb, _, _ = B.amg_eig_status(M)
+    assert fb.all()
+    assert np.array_equal(M.lambdas(), lam_lanczos)
+    assert code == code_l == B.OK and it == it_l and torch.equal(x, xl)
+
+
+def test_deferred_guard_keeps_a_good_bound_and_checks_other_solves():
+    """With a bound above every level's lambda_max the armed guard lets CG run (no
+    restart, iterations within one of Lanczos); vcycle_apply first runs the deferred
+    smoother test, which passes."""
+    m, A, plan, HA, M = _q1_gpu(10, 4, eig=B.EIG_MLP, guard=B.GUARD_PCG)
+    b = dev(synth.rhs(m, 3))
+    xl = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    _, it_l, _ = B.pcg_solve(HA, M, b, xl, rtol=1e-8)
+    lam_true = B.amg_judge_lambdas(M, 50)[:, 0]
+    B.amg_set_eig_model(M, _const_model(1.05 * lam_true.max()))
+    B.amg_smoother_refresh(M)
+    assert B.amg_guard_status(M) == (True, 0)
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+    assert code == B.OK and rel <= 1e-8 and B.amg_guard_status(M) == (True, 0)
+    z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, b, z)
+    fb, g, _ = B.amg_eig_status(M)
+    assert B.amg_guard_status(M) == (False, 0) and not fb.any() and np.all(g[:, 0] > 0) and np.all(g[:, 0] < 1)
+    del it_l
 
 
 def test_model_validation_and_missing_model():
