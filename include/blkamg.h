@@ -185,8 +185,14 @@ int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream);
  *     ptap_numeric computes only its blocks with column >= row and stores each
  *     off-diagonal one a second time, transposed.  Results on a non-symmetric A are
  *     undefined (the lower triangle mirrors the upper one).
+ *   BLKAMG_PTAP_HOST_SYMBOLIC - build the plan on the host.  By default the patterns
+ *     of A P and A_c and the contribution lists are built on the device (paper §6:
+ *     the device-resident setup), one sorted row per workgroup; a row with more than
+ *     4096 contributions makes the whole build fall back to the host.  Both builds
+ *     produce the same plan, so ptap_numeric gives the same bits either way.
  * Unknown flags are EINVAL. */
 #define BLKAMG_PTAP_SYMMETRIC 1
+#define BLKAMG_PTAP_HOST_SYMBOLIC 2
 int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream);
 /* Numeric phase: C.values = P^T A P on the fixed pattern.  If P's value stamp
  * differs from the one cached, the prolongator-side cache (transpose values) is

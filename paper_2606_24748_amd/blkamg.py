@@ -326,6 +326,7 @@ def ptap_symbolic(A: Bsr, P: Bsr, stream=None) -> Bsr:
 
 
 PTAP_SYMMETRIC = 1
+PTAP_HOST_SYMBOLIC = 2
 
 
 def ptap_symbolic_ex(A: Bsr, P: Bsr, flags: int, stream=None) -> Bsr:

@@ -51,6 +51,28 @@ std::unique_ptr<bsr_s> make_owned(int32_t nbr, int32_t nbc, int32_t br, int32_t 
   return A;
 }
 
+std::unique_ptr<bsr_s> make_owned_device(int32_t nbr, int32_t nbc, int32_t br, int32_t bc, int dtype,
+                                         DevBuf<int32_t>&& d_rowptr, DevBuf<int32_t>&& d_colidx, int64_t nnzb,
+                                         hipStream_t s) {
+  auto A = std::make_unique<bsr_s>();
+  A->nbr = nbr;
+  A->nbc = nbc;
+  A->br = br;
+  A->bc = bc;
+  A->dtype = dtype;
+  A->nnzb = nnzb;
+  A->own_rowptr = std::move(d_rowptr);
+  A->own_colidx = std::move(d_colidx);
+  A->own_val.alloc(A->val_bytes());
+  if (A->own_val.p) HIP_CHECK(hipMemsetAsync(A->own_val.p, 0, A->val_bytes(), s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  A->rowptr = A->own_rowptr.p;
+  A->colidx = A->own_colidx.p;
+  A->val = A->own_val.p;
+  A->h_pattern = false;  // downloaded on demand
+  return A;
+}
+
 void ensure_host_pattern(bsr_s* A) {
   if (A->h_pattern) return;
   A->h_rowptr = download(A->rowptr, static_cast<size_t>(A->nbr) + 1);

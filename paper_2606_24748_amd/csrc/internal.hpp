@@ -52,6 +52,11 @@ namespace blk {
 // Library-owned matrix with the given host pattern (uploaded) and zeroed values.
 std::unique_ptr<bsr_s> make_owned(int32_t nbr, int32_t nbc, int32_t br, int32_t bc, int dtype,
                                   std::vector<int32_t> h_rowptr, std::vector<int32_t> h_colidx);
+// Library-owned matrix over device pattern arrays (taken over) and zeroed values; its
+// host pattern is downloaded on demand.  Sync.
+std::unique_ptr<bsr_s> make_owned_device(int32_t nbr, int32_t nbc, int32_t br, int32_t bc, int dtype,
+                                         DevBuf<int32_t>&& d_rowptr, DevBuf<int32_t>&& d_colidx, int64_t nnzb,
+                                         hipStream_t s);
 // Make sure A->h_rowptr / h_colidx hold the pattern (downloads once; sync).
 void ensure_host_pattern(bsr_s* A);
 // Transpose cache of A, built if needed; values refreshed on `s` if stale.

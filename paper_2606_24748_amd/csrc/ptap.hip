@@ -12,43 +12,10 @@
 #include <string>
 #include <type_traits>
 
+#include "ptap_plan.hpp"
 #include "spmv_core.hpp"
 
 namespace blk {
-
-// Contributions to one output block, listed once at symbolic time: each entry packs
-// (index within the first operand's row, index within the second operand's row)
-// into `width` bytes, high part shifted left by `shift`.
-struct PairList {
-  DevBuf<uint8_t> codes;
-  DevBuf<int32_t> ptr;  // ptr[s]..ptr[s+1]: entries of output block s
-  int width = 0;        // 1, 2 or 4 bytes; 0 = not built (use the searching kernels)
-  int shift = 0;
-};
-
-struct PtapPlan {
-  const bsr_s* A = nullptr;
-  const bsr_s* P = nullptr;
-  int64_t a_nnzb = 0, p_nnzb = 0;
-  int32_t n_ap_rows = 0;
-  DevBuf<int32_t> ap_rowptr, ap_colidx;
-  DevBuf<char> ap_val;  // scratch for A P in the accumulation type
-  int g_ap = 32, g_c = 32;
-  PairList ap_pairs;    // per AP block: (block of A row i, block of P row j)
-  PairList c_pairs;     // per C block: (entry of R row a, block of AP row i)
-  int64_t ap_nslots = 0;
-  DevBuf<int32_t> ap_slot_row0, c_slot_row0;  // row of the first block of each workgroup
-  DevBuf<uint8_t> ap_perm, c_perm;             // per workgroup: order in which lanes take the blocks
-  int ap_cap = 0, c_cap = 0;                   // LDS capacity (entries of X rows) of a workgroup
-  int ap_nl = 1, c_nl = 1;                     // lanes per output block (1 or 3)
-  int ap_xcd = 32, c_xcd = 8;                  // workgroup order: 0 hardware, -1 XCD-contiguous, C > 0 chunks
-  bool ap_vec = true, c_vec = true;
-  // symmetric mode: only blocks with column >= row are computed (upper list), each
-  // off-diagonal one is also stored transposed at its mirror position
-  bool sym = false;
-  int64_t c_nslots = 0;
-  DevBuf<int32_t> c_up_rp, c_up_idx, c_mirror;
-};
 
 namespace {
 
@@ -162,8 +129,6 @@ __global__ __launch_bounds__(kBlock) void rap_kernel(int ncoarse, const int32_t*
 // time from the workgroups' extents (`cap` entries), so small blocks (FP32) leave room
 // for more resident workgroups.  Y blocks are read with 16-byte (FP64) or 8-byte (FP32)
 // vector loads when VEC is set.
-constexpr int kMaxR = 48;
-constexpr int kLdsBytes = 49152;  // per workgroup
 #ifndef BLK_AP_XSTAGE_F64
 #define BLK_AP_XSTAGE_F64 1
 #endif
@@ -708,6 +673,39 @@ std::vector<int32_t> first_rows(const std::vector<int32_t>& rp, int per) {
   return out;
 }
 
+// Tuning switches of the numeric plan (environment BLKAMG_PTAP_TUNE, default "ap_sort";
+// flags ap_sort / c_sort / ap_nl1 / c_nl1 / c_nl3 / ap_novec / c_novec / nostage /
+// ap_xcd[=C] / c_xcd[=C]).
+struct PtapTune {
+  std::string tn;
+  bool has(const char* f) const { return tn.find(f) != std::string::npos; }
+  int chunk_of(const char* key, int dflt) const {
+    const size_t at = tn.find(key);
+    if (at == std::string::npos) return dflt;
+    const char* v = tn.c_str() + at + std::strlen(key);
+    return *v == '=' ? std::max(0, std::atoi(v + 1)) : -1;
+  }
+};
+
+// Plan settings that do not depend on the patterns.
+void plan_settings(PtapPlan& pl, const bsr_s* A, const PtapTune& t) {
+  // Measured at 128^3: three lanes per block shorten every A P pass (FP64 fine level
+  // 8.0 -> 5.6 ms) and the 6x6 R AP passes; the fine FP32 R AP pass is faster with
+  // one lane per block (2.1 vs 2.3 ms).
+  // workgroup order: the hardware's round-robin over XCDs by default (measured at 128^3:
+  // 4-6 % faster for the fine passes than XCD-contiguous ranges, whose eight separate
+  // working sets overflow the shared MALL); ap_xcd / c_xcd switch back
+  // (ap_xcd / c_xcd: XCD-contiguous ranges; ap_xcd=C / c_xcd=C: chunks of C; measured at
+  // 128^3, runs of 32 (A P) and 8 (R AP) workgroups per XCD are 1-3 % faster again than
+  // the hardware order)
+  pl.ap_xcd = t.chunk_of("ap_xcd", 32);
+  pl.c_xcd = t.chunk_of("c_xcd", 8);
+  pl.ap_nl = t.has("ap_nl1") ? 1 : 3;
+  pl.c_nl = t.has("c_nl1") ? 1 : t.has("c_nl3") ? 3 : (A->dtype == BLKAMG_F32 && A->br == 3 ? 1 : 3);
+  pl.ap_vec = !t.has("ap_novec");
+  pl.c_vec = !t.has("c_novec");
+}
+
 }  // namespace
 
 }  // namespace blk
@@ -720,7 +718,8 @@ int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream) { return ptap_symbol
 
 int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
   BLK_API_BEGIN
-  BLK_REQUIRE((flags & ~BLKAMG_PTAP_SYMMETRIC) == 0, BLKAMG_EINVAL, "unknown ptap flags");
+  BLK_REQUIRE((flags & ~(BLKAMG_PTAP_SYMMETRIC | BLKAMG_PTAP_HOST_SYMBOLIC)) == 0, BLKAMG_EINVAL,
+              "unknown ptap flags");
   BLK_REQUIRE(A != nullptr && P != nullptr && C != nullptr, BLKAMG_EINVAL, "NULL argument");
   *C = nullptr;
   BLK_REQUIRE(A->br == A->bc && A->br == P->br, BLKAMG_EINVAL, "A must be square-blocked with bs = P.bs_r");
@@ -732,9 +731,37 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
               BLKAMG_EINVAL, "dtype combination must be F64/F64, F32/F32 or F32/BF16");
   hipStream_t s = as_stream(stream);
   HIP_CHECK(hipStreamSynchronize(s));
-  ensure_host_pattern(A);
+  const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
+  const PtapTune tn{tune ? tune : "ap_sort"};
+  const bool search = std::getenv("BLKAMG_PTAP_SEARCH") != nullptr;
+  const size_t acc_size = A->dtype == BLKAMG_F64 ? 8 : 4;
   ensure_host_pattern(P);
   bsr_s* R = transpose_of(P, s);
+  if (!search && !(flags & BLKAMG_PTAP_HOST_SYMBOLIC)) {
+    auto plan = std::make_shared<PtapPlan>();
+    plan->A = A;
+    plan->P = P;
+    plan->a_nnzb = A->nnzb;
+    plan->p_nnzb = P->nnzb;
+    plan->n_ap_rows = A->nbr;
+    plan->sym = (flags & BLKAMG_PTAP_SYMMETRIC) != 0;
+    plan_settings(*plan, A, tn);
+    DevBuf<int32_t> crp, cci;
+    int64_t cnnz = 0;
+    if (ptap_symbolic_device(A, P, R, *plan, tn.has("ap_sort"), tn.has("c_sort"), crp, cci, cnnz, s)) {
+      BLK_REQUIRE(cnnz <= INT32_MAX, BLKAMG_EINVAL, "coarse pattern too large");
+      plan->g_ap = pick_lanes(A->nbr ? static_cast<double>(plan->ap_nslots) / A->nbr : 0.0);
+      plan->g_c = pick_lanes(P->nbc ? static_cast<double>(cnnz) / P->nbc : 0.0);
+      plan->ap_val.alloc(static_cast<size_t>(plan->ap_nslots) * P->br * P->bc * acc_size);
+      if (tn.has("nostage")) plan->ap_cap = plan->c_cap = 1;
+      auto Cm = make_owned_device(P->nbc, P->nbc, P->bc, P->bc, A->dtype, std::move(crp), std::move(cci), cnnz, s);
+      Cm->ext = plan;
+      *C = Cm.release();
+      return BLKAMG_OK;
+    }
+  }
+  // host build
+  ensure_host_pattern(A);
   auto plan = std::make_shared<PtapPlan>();
   std::vector<int32_t> aprp, apci, crp, cci;
   structural_product_host(A->nbr, A->h_rowptr, A->h_colidx, P->nbc, P->h_rowptr, P->h_colidx, aprp, apci);
@@ -746,11 +773,10 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
   plan->n_ap_rows = A->nbr;
   plan->g_ap = pick_lanes(A->nbr ? static_cast<double>(apci.size()) / A->nbr : 0.0);
   plan->g_c = pick_lanes(P->nbc ? static_cast<double>(cci.size()) / P->nbc : 0.0);
-  const size_t acc_size = A->dtype == BLKAMG_F64 ? 8 : 4;
   plan->ap_val.alloc(apci.size() * static_cast<size_t>(P->br) * P->bc * acc_size);
   upload(plan->ap_rowptr, aprp);
   upload(plan->ap_colidx, apci);
-  if (!std::getenv("BLKAMG_PTAP_SEARCH")) {
+  if (!search) {
     build_pairs(A->nbr, P->nbc, A->h_rowptr, A->h_colidx, P->h_rowptr, P->h_colidx, aprp, apci, true, plan->ap_pairs);
     plan->sym = (flags & BLKAMG_PTAP_SYMMETRIC) != 0;
     std::vector<int32_t> orp = crp, oci = cci;  // output blocks of the R*AP pass
@@ -784,29 +810,7 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     build_pairs(R->nbr, P->nbc, R->h_rowptr, R->h_colidx, aprp, apci, orp, oci, true, plan->c_pairs);
     if (!plan->c_pairs.width) plan->sym = false;  // the searching kernel computes every block
     plan->ap_nslots = static_cast<int64_t>(apci.size());
-    // lanes per output block (tuning switches ap_nl1 / ap_nl3 / c_nl1 / c_nl3)
-    const char* tune = std::getenv("BLKAMG_PTAP_TUNE");
-    const std::string tn = tune ? tune : "ap_sort";
-    auto has = [&](const char* f) { return tn.find(f) != std::string::npos; };
-    // Measured at 128^3: three lanes per block shorten every A P pass (FP64 fine level
-    // 8.0 -> 5.6 ms) and the 6x6 R AP passes; the fine FP32 R AP pass is faster with
-    // one lane per block (2.1 vs 2.3 ms).
-    // workgroup order: the hardware's round-robin over XCDs by default (measured at 128^3:
-    // 4-6 % faster for the fine passes than XCD-contiguous ranges, whose eight separate
-    // working sets overflow the shared MALL); ap_xcd / c_xcd switch back
-    // (ap_xcd / c_xcd: XCD-contiguous ranges; ap_xcd=C / c_xcd=C: chunks of C; measured at
-    // 128^3, runs of 32 (A P) and 8 (R AP) workgroups per XCD are 1-3 % faster again than
-    // the hardware order)
-    auto chunk_of = [&](const char* key, int dflt) {
-      const size_t at = tn.find(key);
-      if (at == std::string::npos) return dflt;
-      const char* v = tn.c_str() + at + std::strlen(key);
-      return *v == '=' ? std::max(0, std::atoi(v + 1)) : -1;
-    };
-    plan->ap_xcd = chunk_of("ap_xcd", 32);
-    plan->c_xcd = chunk_of("c_xcd", 8);
-    plan->ap_nl = has("ap_nl1") ? 1 : 3;
-    plan->c_nl = has("c_nl1") ? 1 : has("c_nl3") ? 3 : (A->dtype == BLKAMG_F32 && A->br == 3 ? 1 : 3);
+    plan_settings(*plan, A, tn);
     const int ap_spw = kBlock / plan->ap_nl, c_spw = kBlock / plan->c_nl;
     const std::vector<int32_t> ap_w = first_rows(aprp, ap_spw), c_w = first_rows(orp, c_spw);
     upload(plan->ap_slot_row0, ap_w);
@@ -832,17 +836,14 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
     };
     plan->ap_cap = cap_of(ap_w, A->h_rowptr, A->nbr, 4 + static_cast<size_t>(A->br) * A->br * dtype_size(A->dtype));
     plan->c_cap = cap_of(c_w, R->h_rowptr, R->nbr, 4);
-    if (has("nostage")) plan->ap_cap = plan->c_cap = 1;  // every workgroup takes the global-memory path
-    // more tuning switches: ap_sort, c_sort, ap_novec, c_novec
-    plan->ap_vec = !has("ap_novec");
-    plan->c_vec = !has("c_novec");
+    if (tn.has("nostage")) plan->ap_cap = plan->c_cap = 1;  // every workgroup takes the global-memory path
     if (plan->ap_pairs.width) {
       std::vector<int32_t> hp = download(plan->ap_pairs.ptr.p, plan->ap_pairs.ptr.n);
-      upload(plan->ap_perm, has("ap_sort") ? count_order(hp, ap_spw) : identity_order(hp.size() - 1, ap_spw));
+      upload(plan->ap_perm, tn.has("ap_sort") ? count_order(hp, ap_spw) : identity_order(hp.size() - 1, ap_spw));
     }
     if (plan->c_pairs.width) {
       std::vector<int32_t> hp = download(plan->c_pairs.ptr.p, plan->c_pairs.ptr.n);
-      upload(plan->c_perm, has("c_sort") ? count_order(hp, c_spw) : identity_order(hp.size() - 1, c_spw));
+      upload(plan->c_perm, tn.has("c_sort") ? count_order(hp, c_spw) : identity_order(hp.size() - 1, c_spw));
     }
   }
   auto Cm = make_owned(P->nbc, P->nbc, P->bc, P->bc, A->dtype, std::move(crp), std::move(cci));

@@ -334,3 +334,42 @@ def test_spmv_sym_on_the_elasticity_operator_and_refusals():
     HU, _ = to_device_bsr(U)
     with pytest.raises(B.BlkAmgError):
         B.bsr_spmv_sym(HU, 1.0, dev(np.zeros(9)), 0.0, torch.zeros(9, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("case", ["q1_sym", "q1_full", "rand6_sym", "rand3_empty_rows", "f32_sym", "c_sort_nostage"])
+def test_ptap_device_symbolic_equals_host_build(case, monkeypatch):
+    """The symbolic phase built on the device (default) and on the host
+    (PTAP_HOST_SYMBOLIC) give the same coarse pattern and, through the same contribution
+    order, the same numeric bits; both match the oracle's P^T A P."""
+    print(f"device symbolic case={case}", flush=True)
+    dt, flags = B.F64, B.PTAP_SYMMETRIC
+    if case.startswith("q1") or case == "f32_sym" or case == "c_sort_nostage":
+        m, i, j, v, A = q1_problem(9, 3)
+        from oracle import solve
+        P = solve.setup(A, m.coords, m.dirichlet, solve.Options(coarse_eq_limit=50)).levels[0].P
+        if case == "q1_full":
+            flags = 0
+        if case == "f32_sym":
+            dt = B.F32
+        if case == "c_sort_nostage":
+            monkeypatch.setenv("BLKAMG_PTAP_TUNE", "ap_sort,c_sort,nostage")
+    elif case == "rand6_sym":
+        rp, ci, vv = synth.random_spd_bsr(500, 6, seed=41, max_per_row=12)
+        A = S.Bsr(500, 500, 6, 6, rp.astype(np.int64), ci.astype(np.int64), vv)
+        P = _rand(500, 63, 6, 6, seed=42, max_per_row=4)
+    else:
+        A = _rand(600, 600, 3, 3, seed=43, max_per_row=20, empty_row_frac=0.1)
+        P = _rand(600, 70, 3, 6, seed=44, max_per_row=5, empty_row_frac=0.2)
+        flags = 0
+    HA, _ = to_device_bsr(A, dt)
+    HP, _ = to_device_bsr(P, dt)
+    Cd = B.ptap_symbolic_ex(HA, HP, flags)
+    Ch = B.ptap_symbolic_ex(HA, HP, flags | B.PTAP_HOST_SYMBOLIC)
+    B.ptap_numeric(HA, HP, Cd)
+    B.ptap_numeric(HA, HP, Ch)
+    gd, gh = from_device_bsr(Cd), from_device_bsr(Ch)
+    want = S.ptap(A, P)
+    assert np.array_equal(gd.rowptr, want.rowptr) and np.array_equal(gd.colidx, want.colidx)
+    assert np.array_equal(gd.rowptr, gh.rowptr) and np.array_equal(gd.colidx, gh.colidx)
+    assert np.array_equal(gd.val, gh.val)
+    assert rel2(gd.val, want.val) <= (1e-12 if dt == B.F64 else 1e-5)
