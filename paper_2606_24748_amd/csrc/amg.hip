@@ -1265,16 +1265,27 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     check_flags(M.get(), s);
     std::vector<double> omega_seg;
     setup_level_scalars(M.get(), l, omega_seg, s);
-    // smoothed prolongator: pattern of A P~ on the host, values on the device
+    // smoothed prolongator: pattern of A P~ (structural product on the device, or on the
+    // host for rows beyond the device product's limit), values on the device
     bsr_s* A = L.A_act.get();
     std::vector<int32_t> ptrp(static_cast<size_t>(A->nbr) + 1, 0), ptci;
     for (int32_t i = 0; i < A->nbr; ++i) {
       if (L.agg[i] >= 0) ptci.push_back(L.agg[i]);
       ptrp[i + 1] = static_cast<int32_t>(ptci.size());
     }
-    std::vector<int32_t> prp, pci;
-    structural_product_host(A->nbr, A->h_rowptr, A->h_colidx, n_agg, ptrp, ptci, prp, pci);
-    L.P = make_owned(A->nbr, n_agg, A->br, nc_bs, BLKAMG_F64, std::move(prp), std::move(pci));
+    {
+      DevBuf<int32_t> dtrp, dtci, prp_d, pci_d;
+      upload(dtrp, ptrp);
+      upload(dtci, ptci);
+      int64_t pnnz = 0;
+      if (structural_product_device(A->nbr, A->rowptr, A->colidx, dtrp.p, dtci.p, prp_d, pci_d, pnnz, s)) {
+        L.P = make_owned_device(A->nbr, n_agg, A->br, nc_bs, BLKAMG_F64, std::move(prp_d), std::move(pci_d), pnnz, s);
+      } else {
+        std::vector<int32_t> prp, pci;
+        structural_product_host(A->nbr, A->h_rowptr, A->h_colidx, n_agg, ptrp, ptci, prp, pci);
+        L.P = make_owned(A->nbr, n_agg, A->br, nc_bs, BLKAMG_F64, std::move(prp), std::move(pci));
+      }
+    }
     {
       DevBuf<double> dom;
       upload(dom, omega_seg);

@@ -396,6 +396,17 @@ void group_tables(const Product& o, const PairList& pl, int nrows, const int32_t
 
 }  // namespace
 
+bool structural_product_device(int32_t nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t* y_rp,
+                               const int32_t* y_ci, DevBuf<int32_t>& out_rp, DevBuf<int32_t>& out_ci, int64_t& nnz,
+                               hipStream_t s) {
+  Product o;
+  if (!product(nrows, x_rp, x_ci, y_rp, y_ci, false, nullptr, o, s)) return false;
+  nnz = o.nout;
+  out_rp = std::move(o.rp);
+  out_ci = std::move(o.ci);
+  return true;
+}
+
 bool ptap_symbolic_device(const bsr_s* A, const bsr_s* P, const bsr_s* R, PtapPlan& plan, bool ap_sort,
                           bool c_sort, DevBuf<int32_t>& c_rowptr, DevBuf<int32_t>& c_colidx, int64_t& c_nnzb,
                           hipStream_t s) {
