@@ -737,7 +737,7 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream) {
   const size_t acc_size = A->dtype == BLKAMG_F64 ? 8 : 4;
   ensure_host_pattern(P);
   bsr_s* R = transpose_of(P, s);
-  if (!search && !(flags & BLKAMG_PTAP_HOST_SYMBOLIC)) {
+  if (!search && !(flags & BLKAMG_PTAP_HOST_SYMBOLIC) && !tn.has("host_symbolic")) {
     auto plan = std::make_shared<PtapPlan>();
     plan->A = A;
     plan->P = P;
