@@ -187,8 +187,9 @@ int ptap_symbolic(bsr_t A, bsr_t P, bsr_t* C, void* stream);
  *     undefined (the lower triangle mirrors the upper one).
  *   BLKAMG_PTAP_HOST_SYMBOLIC - build the plan on the host.  By default the patterns
  *     of A P and A_c and the contribution lists are built on the device (paper §6:
- *     the device-resident setup), one sorted row per workgroup; a row with more than
- *     4096 contributions makes the whole build fall back to the host.  Both builds
+ *     the device-resident setup): each output row's contributions are sorted in LDS by
+ *     one workgroup, or, beyond 4096 of them, in device memory by a segmented radix
+ *     sort.  Both builds
  *     produce the same plan, so ptap_numeric gives the same bits either way.
  * Unknown flags are EINVAL. */
 #define BLKAMG_PTAP_SYMMETRIC 1

@@ -1278,7 +1278,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
       upload(dtrp, ptrp);
       upload(dtci, ptci);
       int64_t pnnz = 0;
-      if (structural_product_device(A->nbr, A->rowptr, A->colidx, dtrp.p, dtci.p, prp_d, pci_d, pnnz, s)) {
+      if (structural_product_device(A->nbr, n_agg, A->rowptr, A->colidx, dtrp.p, dtci.p, prp_d, pci_d, pnnz, s)) {
         L.P = make_owned_device(A->nbr, n_agg, A->br, nc_bs, BLKAMG_F64, std::move(prp_d), std::move(pci_d), pnnz, s);
       } else {
         std::vector<int32_t> prp, pci;

@@ -83,11 +83,12 @@ int autotune_lanes(bsr_s* A, int vdt, int nrhs, hipStream_t s);
 void structural_product_host(int32_t nra, const std::vector<int32_t>& rpa, const std::vector<int32_t>& cia,
                              int32_t ncb, const std::vector<int32_t>& rpb, const std::vector<int32_t>& cib,
                              std::vector<int32_t>& rpc, std::vector<int32_t>& cic);
-// Structural product of two device patterns (sorted unique columns per row), built on
-// the device; false when a row has more than 4096 products (nothing built).  Sync.
-bool structural_product_device(int32_t nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t* y_rp,
-                               const int32_t* y_ci, DevBuf<int32_t>& out_rp, DevBuf<int32_t>& out_ci, int64_t& nnz,
-                               hipStream_t s);
+// Structural product of two device patterns (sorted unique columns per row; Y has
+// ncols columns), built on the device; false when a row of X is longer than 65536
+// entries or a row of Y longer than 65536 (nothing built).  Sync.
+bool structural_product_device(int32_t nrows, int32_t ncols, const int32_t* x_rp, const int32_t* x_ci,
+                               const int32_t* y_rp, const int32_t* y_ci, DevBuf<int32_t>& out_rp,
+                               DevBuf<int32_t>& out_ci, int64_t& nnz, hipStream_t s);
 // Cast a value array between dtypes on the device.
 void cast_values(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
 // Tentative prolongator rows and coarse near-null space on the device (per-aggregate

@@ -51,10 +51,9 @@ struct PtapPlan {
 // device (same contents as the host build).  Fills plan->ap_rowptr / ap_colidx /
 // ap_pairs / c_pairs / c_up_* / *_slot_row0 / *_perm / *_cap / ap_nslots / c_nslots
 // and the coarse pattern (c_rowptr, c_colidx on the device, c_nnzb).  plan->sym,
-// ap_nl and c_nl must be set.  Returns false, with nothing usable built, when some
-// output row has more than 4096 contributions (one workgroup sorts a row in LDS; the
-// caller then builds on the host).  EINVAL when sym is set and the coarse pattern is not
-// symmetric.  Sync.
+// ap_nl and c_nl must be set.  Returns false, with nothing usable built, when a row
+// offset does not fit 16 bits (the caller then builds on the host).  EINVAL when sym
+// is set and the coarse pattern is not symmetric.  Sync.
 bool ptap_symbolic_device(const bsr_s* A, const bsr_s* P, const bsr_s* R, PtapPlan& plan, bool ap_sort,
                           bool c_sort, DevBuf<int32_t>& c_rowptr, DevBuf<int32_t>& c_colidx, int64_t& c_nnzb,
                           hipStream_t s);

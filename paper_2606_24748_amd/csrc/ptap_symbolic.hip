@@ -64,17 +64,99 @@ __global__ __launch_bounds__(256) void prod_count_kernel(int nrows, const int32_
   }
 }
 
-// One workgroup (one wave) per output row, rows strided over the grid.  LDS: keys[p2cap]
-// (column << 32 | generation index) and pay[p2cap] (k offset << 16 | q offset).
-// COUNT: n_out[r] = number of distinct columns.  Otherwise (fill): the row's output
-// columns at out_ci[out_rp[r]..], and with pairs, pp[output] = cand_off[r] + the start
-// of its run and the codes (k offset << shift | q offset, WIDTH bytes little endian) at
-// codes[(cand_off[r] + position) * WIDTH].
+// The candidates of output row r in (k, q) order: keys[pos] = column << 32 | pos and
+// pay[pos] = k offset << 16 | q offset, pos = 0 .. n-1 (keys and pay in LDS, or a
+// row's slice of a device buffer).  One 64-lane wave; returns n.
+template <bool UPPER>
+__device__ __forceinline__ int gen_row(int r, const int32_t* __restrict__ x_rp, const int32_t* __restrict__ x_ci,
+                                       const int32_t* __restrict__ y_rp, const int32_t* __restrict__ y_ci,
+                                       uint64_t* keys, uint32_t* pay, int lane) {
+  const int k0 = x_rp[r], k1 = x_rp[r + 1];
+  int base = 0;
+  for (int kb = k0; kb < k1; kb += 64) {
+    const int k = kb + lane;
+    int c = 0, q0 = 0, q1 = 0;
+    if (k < k1) {
+      const int j = x_ci[k];
+      q0 = y_rp[j];
+      q1 = y_rp[j + 1];
+      if (UPPER) {
+        for (int q = q0; q < q1; ++q) c += y_ci[q] >= r ? 1 : 0;
+      } else {
+        c = q1 - q0;
+      }
+    }
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    int pos = base + incl - c;
+    for (int q = q0; q < q1; ++q) {
+      const int col = y_ci[q];
+      if (UPPER && col < r) continue;
+      keys[pos] = (static_cast<uint64_t>(static_cast<uint32_t>(col)) << 32) | static_cast<uint32_t>(pos);
+      pay[pos] = (static_cast<uint32_t>(k - k0) << 16) | static_cast<uint32_t>(q - q0);
+      ++pos;
+    }
+    base += __shfl(incl, 63, 64);
+  }
+  return base;
+}
+
+// From the n sorted candidates of row r: COUNT, n_out[r] = number of distinct columns;
+// otherwise (fill) the row's output columns at out_ci[out_rp[r]..] and, with pairs,
+// pp[output] = cand_off[r] + the start of its run and the codes (k offset << shift |
+// q offset, WIDTH bytes little endian) at codes[(cand_off[r] + position) * WIDTH].
+template <bool COUNT, int WIDTH>
+__device__ __forceinline__ void emit_row(int r, int n, const uint64_t* keys, const uint32_t* pay, int lane,
+                                         int32_t* __restrict__ n_out, const int32_t* __restrict__ out_rp,
+                                         int32_t* __restrict__ out_ci, const int64_t* __restrict__ cand_off,
+                                         int32_t* __restrict__ pp, uint8_t* __restrict__ codes, int shift) {
+  int ubase = 0;
+  for (int pb = 0; pb < n; pb += 64) {
+    const int p = pb + lane;
+    const bool valid = p < n;
+    const uint32_t col = valid ? static_cast<uint32_t>(keys[p] >> 32) : 0u;
+    const bool start = valid && (p == 0 || static_cast<uint32_t>(keys[p - 1] >> 32) != col);
+    const uint64_t ball = __ballot(start);
+    if constexpr (!COUNT) {
+      if (start) {
+        const int u = ubase + __popcll(ball & ((1ull << lane) - 1ull));
+        const int oidx = out_rp[r] + u;
+        out_ci[oidx] = static_cast<int32_t>(col);
+        if (pp) pp[oidx] = static_cast<int32_t>(cand_off[r] + p);
+      }
+      if (codes && valid) {
+        const uint32_t pl = pay[static_cast<uint32_t>(keys[p])];
+        const uint32_t code = ((pl >> 16) << shift) | (pl & 0xFFFFu);
+        uint8_t* dst = codes + static_cast<size_t>(cand_off[r] + p) * WIDTH;
+        if constexpr (WIDTH == 1) {
+          dst[0] = static_cast<uint8_t>(code);
+        } else if constexpr (WIDTH == 2) {
+          *reinterpret_cast<uint16_t*>(dst) = static_cast<uint16_t>(code);
+        } else {
+          *reinterpret_cast<uint32_t*>(dst) = code;
+        }
+      }
+    }
+    ubase += __popcll(ball);
+  }
+  if constexpr (COUNT) {
+    if (lane == 0) n_out[r] = ubase;
+  }
+}
+
+// One workgroup (one wave) per output row with at most p2cap candidates, rows strided
+// over the grid (longer rows are left to the device-memory path).  LDS: keys[p2cap]
+// and pay[p2cap]; a bitonic network sorts a row's keys.
 template <bool UPPER, bool COUNT, int WIDTH>
 __global__ __launch_bounds__(64) void prod_sort_kernel(int nrows, const int32_t* __restrict__ x_rp,
                                                        const int32_t* __restrict__ x_ci,
                                                        const int32_t* __restrict__ y_rp,
                                                        const int32_t* __restrict__ y_ci, int p2cap,
+                                                       const int64_t* __restrict__ n_cand,
                                                        int32_t* __restrict__ n_out, const int32_t* __restrict__ out_rp,
                                                        int32_t* __restrict__ out_ci, const int64_t* __restrict__ cand_off,
                                                        int32_t* __restrict__ pp, uint8_t* __restrict__ codes, int shift) {
@@ -83,38 +165,8 @@ __global__ __launch_bounds__(64) void prod_sort_kernel(int nrows, const int32_t*
   uint32_t* pay = reinterpret_cast<uint32_t*>(sym_lds + static_cast<size_t>(p2cap) * 8);
   const int lane = threadIdx.x;
   for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
-    const int k0 = x_rp[r], k1 = x_rp[r + 1];
-    int base = 0;
-    for (int kb = k0; kb < k1; kb += 64) {
-      const int k = kb + lane;
-      int c = 0, q0 = 0, q1 = 0;
-      if (k < k1) {
-        const int j = x_ci[k];
-        q0 = y_rp[j];
-        q1 = y_rp[j + 1];
-        if (UPPER) {
-          for (int q = q0; q < q1; ++q) c += y_ci[q] >= r ? 1 : 0;
-        } else {
-          c = q1 - q0;
-        }
-      }
-      int incl = c;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-      }
-      int pos = base + incl - c;
-      for (int q = q0; q < q1; ++q) {
-        const int col = y_ci[q];
-        if (UPPER && col < r) continue;
-        keys[pos] = (static_cast<uint64_t>(static_cast<uint32_t>(col)) << 32) | static_cast<uint32_t>(pos);
-        pay[pos] = (static_cast<uint32_t>(k - k0) << 16) | static_cast<uint32_t>(q - q0);
-        ++pos;
-      }
-      base += __shfl(incl, 63, 64);
-    }
-    const int n = base;  // <= p2cap (checked by the count pass)
+    if (n_cand[r] > p2cap) continue;  // uniform over the workgroup
+    const int n = gen_row<UPPER>(r, x_rp, x_ci, y_rp, y_ci, keys, pay, lane);
     int p2 = 1;
     while (p2 < n) p2 <<= 1;
     for (int i = n + lane; i < p2; i += 64) keys[i] = ~0ull;
@@ -134,39 +186,37 @@ __global__ __launch_bounds__(64) void prod_sort_kernel(int nrows, const int32_t*
         __syncthreads();
       }
     }
-    int ubase = 0;
-    for (int pb = 0; pb < n; pb += 64) {
-      const int p = pb + lane;
-      const bool valid = p < n;
-      const uint32_t col = valid ? static_cast<uint32_t>(keys[p] >> 32) : 0u;
-      const bool start = valid && (p == 0 || static_cast<uint32_t>(keys[p - 1] >> 32) != col);
-      const uint64_t ball = __ballot(start);
-      if constexpr (!COUNT) {
-        if (start) {
-          const int u = ubase + __popcll(ball & ((1ull << lane) - 1ull));
-          const int oidx = out_rp[r] + u;
-          out_ci[oidx] = static_cast<int32_t>(col);
-          if (pp) pp[oidx] = static_cast<int32_t>(cand_off[r] + p);
-        }
-        if (codes && valid) {
-          const uint32_t pl = pay[static_cast<uint32_t>(keys[p])];
-          const uint32_t code = ((pl >> 16) << shift) | (pl & 0xFFFFu);
-          uint8_t* dst = codes + static_cast<size_t>(cand_off[r] + p) * WIDTH;
-          if constexpr (WIDTH == 1) {
-            dst[0] = static_cast<uint8_t>(code);
-          } else if constexpr (WIDTH == 2) {
-            *reinterpret_cast<uint16_t*>(dst) = static_cast<uint16_t>(code);
-          } else {
-            *reinterpret_cast<uint32_t*>(dst) = code;
-          }
-        }
-      }
-      ubase += __popcll(ball);
-    }
-    if constexpr (COUNT) {
-      if (lane == 0) n_out[r] = ubase;
-    }
+    emit_row<COUNT, WIDTH>(r, n, keys, pay, lane, n_out, out_rp, out_ci, cand_off, pp, codes, shift);
     __syncthreads();  // the next row reuses the LDS
+  }
+}
+
+// Rows beyond the LDS sort: their candidates go to device memory (row li of the list
+// at loff[li]), are sorted there by a segmented radix sort, and emitted like the rest.
+template <bool UPPER>
+__global__ __launch_bounds__(64) void long_gen_kernel(int nlong, const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ loff,
+                                                      const int32_t* __restrict__ x_rp,
+                                                      const int32_t* __restrict__ x_ci,
+                                                      const int32_t* __restrict__ y_rp,
+                                                      const int32_t* __restrict__ y_ci, uint64_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ pay) {
+  for (int li = blockIdx.x; li < nlong; li += gridDim.x)
+    gen_row<UPPER>(rows[li], x_rp, x_ci, y_rp, y_ci, keys + loff[li], pay + loff[li], threadIdx.x);
+}
+
+template <bool COUNT, int WIDTH>
+__global__ __launch_bounds__(64) void long_emit_kernel(int nlong, const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ loff,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ pay, int32_t* __restrict__ n_out,
+                                                       const int32_t* __restrict__ out_rp, int32_t* __restrict__ out_ci,
+                                                       const int64_t* __restrict__ cand_off, int32_t* __restrict__ pp,
+                                                       uint8_t* __restrict__ codes, int shift) {
+  for (int li = blockIdx.x; li < nlong; li += gridDim.x) {
+    const int64_t o = loff[li];
+    emit_row<COUNT, WIDTH>(rows[li], static_cast<int>(loff[li + 1] - o), keys + o, pay + o, threadIdx.x, n_out,
+                           out_rp, out_ci, cand_off, pp, codes, shift);
   }
 }
 
@@ -290,11 +340,12 @@ struct Product {
   int64_t nout = 0;
 };
 
-// Out = X Y on device patterns (X: nrows rows).  With `pairs`, also the contribution
-// list (codes, per-output starts, width, shift).  False when a row has more than
-// kMaxCand contributions or the codes would not fit 32 bits.
-bool product(int nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t* y_rp, const int32_t* y_ci,
-             bool upper, PairList* pairs, Product& out, hipStream_t s) {
+// Out = X Y on device patterns (X: nrows rows, Y: ncols columns).  With `pairs`, also
+// the contribution list (codes, per-output starts, width, shift).  Rows with up to
+// kMaxCand contributions are sorted in LDS, longer ones in device memory.  False when
+// a row offset does not fit 16 bits or the codes would not fit 32 bits.
+bool product(int nrows, int ncols, const int32_t* x_rp, const int32_t* x_ci, const int32_t* y_rp,
+             const int32_t* y_ci, bool upper, PairList* pairs, Product& out, hipStream_t s) {
   DevBuf<int64_t> ncand(static_cast<size_t>(std::max(nrows, 1)));
   DevBuf<int> maxima(3);
   HIP_CHECK(hipMemsetAsync(maxima.p, 0, 3 * sizeof(int), s));
@@ -307,21 +358,67 @@ bool product(int nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t*
   int mx[3] = {0, 0, 0};
   HIP_CHECK(hipMemcpyAsync(mx, maxima.p, sizeof(mx), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
-  if (mx[2] > kMaxCand || mx[0] >= 65536 || mx[1] >= 65536) return false;
+  if (mx[0] >= 65536 || mx[1] >= 65536) return false;
   int p2cap = 1;
-  while (p2cap < std::max(mx[2], 1)) p2cap <<= 1;
+  while (p2cap < std::min(std::max(mx[2], 1), kMaxCand)) p2cap <<= 1;
   const size_t lds = static_cast<size_t>(p2cap) * 12;
   const int sgrid = std::max(1, std::min(nrows, 65536));
+  // rows beyond the LDS sort: generated into device memory and sorted there (once,
+  // for both the count and the fill)
+  DevBuf<int32_t> lrows;
+  DevBuf<int64_t> loff;
+  DevBuf<uint64_t> lkeys, lsorted;
+  DevBuf<uint32_t> lpay;
+  int nlong = 0;
+  if (mx[2] > kMaxCand) {
+    const std::vector<int64_t> h = download(ncand.p, static_cast<size_t>(nrows), s);
+    std::vector<int32_t> hr;
+    std::vector<int64_t> ho(1, 0);
+    for (int r = 0; r < nrows; ++r)
+      if (h[r] > kMaxCand) {
+        hr.push_back(r);
+        ho.push_back(ho.back() + h[r]);
+      }
+    nlong = static_cast<int>(hr.size());
+    BLK_REQUIRE(ho.back() <= INT32_MAX, BLKAMG_EINVAL, "too many contributions in long rows");
+    const int ntot = static_cast<int>(ho.back());
+    upload(lrows, hr);
+    upload(loff, ho);
+    lkeys.alloc(static_cast<size_t>(ntot));
+    lsorted.alloc(static_cast<size_t>(ntot));
+    lpay.alloc(static_cast<size_t>(ntot));
+    const int lgrid = std::min(nlong, 65536);
+    if (upper)
+      long_gen_kernel<true><<<lgrid, 64, 0, s>>>(nlong, lrows.p, loff.p, x_rp, x_ci, y_rp, y_ci, lkeys.p, lpay.p);
+    else
+      long_gen_kernel<false><<<lgrid, 64, 0, s>>>(nlong, lrows.p, loff.p, x_rp, x_ci, y_rp, y_ci, lkeys.p, lpay.p);
+    HIP_CHECK(hipGetLastError());
+    const int end_bit = 32 + bits_of(std::max(ncols, 1));
+    size_t bytes = 0;
+    HIP_CHECK(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, bytes, lkeys.p, lsorted.p, ntot, nlong, loff.p,
+                                                         loff.p + 1, 0, end_bit, s));
+    DevBuf<char> tmp(std::max<size_t>(bytes, 1));
+    HIP_CHECK(hipcub::DeviceSegmentedRadixSort::SortKeys(tmp.p, bytes, lkeys.p, lsorted.p, ntot, nlong, loff.p,
+                                                         loff.p + 1, 0, end_bit, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    lkeys.release();
+  }
+  const int lgrid = std::max(1, std::min(nlong, 65536));
   DevBuf<int32_t> nout(static_cast<size_t>(std::max(nrows, 1)));
   out.rp.alloc(static_cast<size_t>(nrows) + 1);
   if (nrows > 0) {
     if (upper)
-      prod_sort_kernel<true, true, 1><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, nout.p, nullptr,
-                                                              nullptr, nullptr, nullptr, nullptr, 0);
+      prod_sort_kernel<true, true, 1><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, ncand.p, nout.p,
+                                                              nullptr, nullptr, nullptr, nullptr, nullptr, 0);
     else
-      prod_sort_kernel<false, true, 1><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, nout.p, nullptr,
-                                                               nullptr, nullptr, nullptr, nullptr, 0);
+      prod_sort_kernel<false, true, 1><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, ncand.p, nout.p,
+                                                               nullptr, nullptr, nullptr, nullptr, nullptr, 0);
     HIP_CHECK(hipGetLastError());
+    if (nlong > 0) {
+      long_emit_kernel<true, 1><<<lgrid, 64, 0, s>>>(nlong, lrows.p, loff.p, lsorted.p, lpay.p, nout.p, nullptr,
+                                                     nullptr, nullptr, nullptr, nullptr, 0);
+      HIP_CHECK(hipGetLastError());
+    }
   }
   const int32_t total_out = scan_total<int32_t>(nout.p, out.rp.p, nrows, s);
   out.nout = total_out;
@@ -347,9 +444,14 @@ bool product(int nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t*
   if (nrows > 0 && (total_out > 0 || pairs)) {
     int32_t* pp = pairs ? pairs->ptr.p : nullptr;
     uint8_t* codes = pairs ? pairs->codes.p : nullptr;
-#define BLK_FILL(U, W)                                                                                        \
-  prod_sort_kernel<U, false, W><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, nullptr, out.rp.p, \
-                                                         out.ci.p, coff.p, pp, codes, shift)
+#define BLK_FILL(U, W)                                                                                          \
+  do {                                                                                                          \
+    prod_sort_kernel<U, false, W><<<sgrid, 64, lds, s>>>(nrows, x_rp, x_ci, y_rp, y_ci, p2cap, ncand.p, nullptr, \
+                                                           out.rp.p, out.ci.p, coff.p, pp, codes, shift);       \
+    if (nlong > 0)                                                                                              \
+      long_emit_kernel<false, W><<<lgrid, 64, 0, s>>>(nlong, lrows.p, loff.p, lsorted.p, lpay.p, nullptr,        \
+                                                      out.rp.p, out.ci.p, coff.p, pp, codes, shift);            \
+  } while (0)
     if (upper) {
       if (width == 1) BLK_FILL(true, 1); else if (width == 2) BLK_FILL(true, 2); else BLK_FILL(true, 4);
     } else {
@@ -396,11 +498,11 @@ void group_tables(const Product& o, const PairList& pl, int nrows, const int32_t
 
 }  // namespace
 
-bool structural_product_device(int32_t nrows, const int32_t* x_rp, const int32_t* x_ci, const int32_t* y_rp,
-                               const int32_t* y_ci, DevBuf<int32_t>& out_rp, DevBuf<int32_t>& out_ci, int64_t& nnz,
-                               hipStream_t s) {
+bool structural_product_device(int32_t nrows, int32_t ncols, const int32_t* x_rp, const int32_t* x_ci,
+                               const int32_t* y_rp, const int32_t* y_ci, DevBuf<int32_t>& out_rp,
+                               DevBuf<int32_t>& out_ci, int64_t& nnz, hipStream_t s) {
   Product o;
-  if (!product(nrows, x_rp, x_ci, y_rp, y_ci, false, nullptr, o, s)) return false;
+  if (!product(nrows, ncols, x_rp, x_ci, y_rp, y_ci, false, nullptr, o, s)) return false;
   nnz = o.nout;
   out_rp = std::move(o.rp);
   out_ci = std::move(o.ci);
@@ -413,13 +515,13 @@ bool ptap_symbolic_device(const bsr_s* A, const bsr_s* P, const bsr_s* R, PtapPl
   // A P (every product column an output)
   Product ap;
   PairList ap_pairs;
-  if (!product(A->nbr, A->rowptr, A->colidx, P->rowptr, P->colidx, false, &ap_pairs, ap, s)) return false;
+  if (!product(A->nbr, P->nbc, A->rowptr, A->colidx, P->rowptr, P->colidx, false, &ap_pairs, ap, s)) return false;
   // the coarse pattern R (A P), and the outputs of the R AP pass
   Product cfull, cup;
   PairList c_pairs;
   if (plan.sym) {
-    if (!product(R->nbr, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, false, nullptr, cfull, s)) return false;
-    if (!product(R->nbr, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, true, &c_pairs, cup, s)) return false;
+    if (!product(R->nbr, P->nbc, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, false, nullptr, cfull, s)) return false;
+    if (!product(R->nbr, P->nbc, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, true, &c_pairs, cup, s)) return false;
     DevBuf<int32_t> uidx(static_cast<size_t>(std::max<int64_t>(cup.nout, 1)));
     DevBuf<int32_t> mir(static_cast<size_t>(std::max<int64_t>(cup.nout, 1)));
     DevBuf<int> ok(1);
@@ -438,7 +540,7 @@ bool ptap_symbolic_device(const bsr_s* A, const bsr_s* P, const bsr_s* R, PtapPl
     plan.c_up_idx = std::move(uidx);
     plan.c_mirror = std::move(mir);
   } else {
-    if (!product(R->nbr, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, false, &c_pairs, cfull, s)) return false;
+    if (!product(R->nbr, P->nbc, R->rowptr, R->colidx, ap.rp.p, ap.ci.p, false, &c_pairs, cfull, s)) return false;
   }
   const Product& cout_ = plan.sym ? cup : cfull;
   const int ap_spw = kBlock / plan.ap_nl, c_spw = kBlock / plan.c_nl;

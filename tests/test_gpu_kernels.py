@@ -336,7 +336,8 @@ def test_spmv_sym_on_the_elasticity_operator_and_refusals():
         B.bsr_spmv_sym(HU, 1.0, dev(np.zeros(9)), 0.0, torch.zeros(9, dtype=torch.float64, device="cuda"))
 
 
-@pytest.mark.parametrize("case", ["q1_sym", "q1_full", "rand6_sym", "rand3_empty_rows", "f32_sym", "c_sort_nostage"])
+@pytest.mark.parametrize("case", ["q1_sym", "q1_full", "rand6_sym", "rand3_empty_rows", "f32_sym", "c_sort_nostage",
+                                  "q2_long_rows_sym", "q2_long_rows_full"])
 def test_ptap_device_symbolic_equals_host_build(case, monkeypatch):
     """The symbolic phase built on the device (default) and on the host
     (PTAP_HOST_SYMBOLIC) give the same coarse pattern and, through the same contribution
@@ -353,6 +354,14 @@ def test_ptap_device_symbolic_equals_host_build(case, monkeypatch):
             dt = B.F32
         if case == "c_sort_nostage":
             monkeypatch.setenv("BLKAMG_PTAP_TUNE", "ap_sort,c_sort,nostage")
+    elif case.startswith("q2"):
+        # triquadratic elements at 5^3: coarse rows with up to 4,913 contributions, beyond
+        # the LDS sort (4096), so they take the device-memory sort
+        m, i, j, v, A = q1_problem(5, 3, order=2)
+        from oracle import solve
+        P = solve.setup(A, m.coords, m.dirichlet).levels[0].P
+        if case.endswith("full"):
+            flags = 0
     elif case == "rand6_sym":
         rp, ci, vv = synth.random_spd_bsr(500, 6, seed=41, max_per_row=12)
         A = S.Bsr(500, 500, 6, 6, rp.astype(np.int64), ci.astype(np.int64), vv)

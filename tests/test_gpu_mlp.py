@@ -358,3 +358,33 @@ def test_learned_cold_setup_falls_back_to_lanczos():
     assert np.allclose(om0[:, 0], (4.0 / 3.0) / lam0[:, 0], rtol=1e-15)
     for l in range(M.num_levels() - 1):
         assert torch.equal(M.level(l)[1].arrays()[2], M0.level(l)[1].arrays()[2])
+
+
+@pytest.mark.parametrize("lam_scale", [None, 0.3])
+def test_mlp_refresh_and_judge_on_a_side_stream(lam_scale):
+    """The learned refresh (growth test, fallback decision, host downloads) and the judge
+    queued on a non-default stream give bit for bit the results of the default stream:
+    the packaged model (no fallback) and a far too low constant bound (every level falls
+    back to Lanczos)."""
+    from paper_2606_24748_amd import train_eigmlp
+    print(f"side stream lam_scale={lam_scale}", flush=True)
+    m, A, plan, HA, M = _q1_gpu(12, 8, eig=B.EIG_MLP)
+    if lam_scale is None:
+        model = train_eigmlp.load_model()
+    else:
+        model = _const_model(lam_scale * B.amg_judge_lambdas(M, 50)[0, 0])
+    B.amg_set_eig_model(M, model)
+    res = []
+    for side in (False, True):
+        torch.cuda.synchronize()
+        st = torch.cuda.Stream() if side else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            B.amg_smoother_refresh(M)
+            fb, g, om = B.amg_eig_status(M)
+            lam = M.lambdas().copy()
+            judge = B.amg_judge_lambdas(M, 30)
+        st.synchronize()
+        res.append((fb.copy(), g.copy(), om.copy(), lam, judge.copy()))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    assert res[0][0].all() == (lam_scale is not None)
