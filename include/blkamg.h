@@ -107,19 +107,23 @@ int blkamg_set_allocator(blkamg_alloc_fn alloc_fn, blkamg_free_fn free_fn, void*
  * block sizes; one int32 column index per block).
  * ========================================================================== */
 
-/* Wrap caller-owned device arrays as a block matrix.
+/* Wrap caller-owned device arrays as a block matrix (the blocked storage of paper
+ * §2.3, §4.2).
  *   nbr, nbc     : block rows / block columns (>= 0)
  *   bs_r, bs_c   : block shape, each in 1..8
  *   nnzb         : stored blocks; d_rowptr[nbr] must equal nnzb
  *   d_rowptr     : int32[nbr+1], d_colidx: int32[nnzb] (ascending within a row)
  *   d_val        : nnzb * bs_r * bs_c values of type `dtype`
+ *   stream       : orders the optional validation after the caller's work that
+ *                  writes the arrays (NULL = the null stream)
  * Borrowed: the handle stores the pointers only.  Validation of the pattern
  * (monotone rowptr, column range, sorted rows) is done when the environment
- * variable BLKAMG_VALIDATE=1 is set (sync, copies the pattern to the host).
- * Errors: EINVAL for bad sizes/pointers.  Host-only; no device work otherwise. */
+ * variable BLKAMG_VALIDATE=1 is set (copies the pattern to the host after the
+ * stream's work, sync).  Errors: EINVAL for bad sizes/pointers.  Host-only; no
+ * device work otherwise. */
 int bsr_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t nnzb,
                const int32_t* d_rowptr, const int32_t* d_colidx, void* d_val,
-               int dtype, bsr_t* out);
+               int dtype, void* stream, bsr_t* out);
 /* Free the handle and everything it owns (caches; for library-created matrices
  * also the arrays).  NULL is accepted. */
 int bsr_destroy(bsr_t A);
@@ -509,6 +513,11 @@ int amg_hierarchy_update(amg_t M, const float* h_lambda, void* stream);
  * [n_dof(A0)][nrhs], nrhs 1 or 8 (F32 hierarchies convert at entry and exit).
  * Async (the first call with nrhs = 8 allocates the wider work vectors). */
 int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* stream);
+/* vcycle_apply with the vectors' type: vec_dtype BLKAMG_F64 (as vcycle_apply, any
+ * hierarchy) or BLKAMG_F32 (F32 hierarchies only: the V-cycle reads d_r and writes
+ * d_z, FP32 [n_dof][nrhs], directly, with no conversion; EINVAL on an F64 hierarchy).
+ * Async. */
+int vcycle_apply_ex(amg_t M, const void* d_r, void* d_z, int vec_dtype, int32_t nrhs, void* stream);
 
 /* Preconditioned CG on A x = b (the CG accelerator of paper §4.1) from x0 = 0 with
  * M = one V-cycle; stops when the recurrence residual satisfies

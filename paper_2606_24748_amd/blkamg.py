@@ -72,7 +72,7 @@ _SIG = {
     "blkamg_last_error": (C.c_char_p, []),
     "blkamg_version": (C.c_int, []),
     "blkamg_set_allocator": (C.c_int, [_p, _p, _p]),
-    "bsr_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, _p, C.c_int, C.POINTER(_p)]),
+    "bsr_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, _p, C.c_int, _p, C.POINTER(_p)]),
     "bsr_destroy": (C.c_int, [_p]),
     "bsr_mark_modified": (C.c_int, [_p]),
     "bsr_info": (C.c_int, [_p, _pi32, _pi32, _pi32, _pi32, C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(_u64)]),
@@ -80,6 +80,7 @@ _SIG = {
     "bsr_spmv": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_spmv_t": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
     "bsr_spmv_sym": (C.c_int, [_p, _f64, _p, _f64, _p, C.c_int, _i32, _p]),
+    "vcycle_apply_ex": (C.c_int, [_p, _p, _p, C.c_int, _i32, _p]),
     "bsr_autotune": (C.c_int, [_p, C.c_int, _i32, _p, _pi32]),
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
     "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
@@ -270,12 +271,12 @@ def _hip():
     return _HIP
 
 
-def bsr_create(nbr, nbc, bs_r, bs_c, rowptr, colidx, val) -> Bsr:
+def bsr_create(nbr, nbc, bs_r, bs_c, rowptr, colidx, val, stream=None) -> Bsr:
     """Wrap torch device tensors (int32 rowptr/colidx, float64/float32/bfloat16 values)."""
     h = _p()
     nnzb = int(colidx.numel())
     _check(_lib.bsr_create(nbr, nbc, bs_r, bs_c, nnzb, _ptr(rowptr), _ptr(colidx), _ptr(val),
-                           dtype_code(val), C.byref(h)), "bsr_create")
+                           dtype_code(val), _stream(stream), C.byref(h)), "bsr_create")
     return Bsr(h, keep=(rowptr, colidx, val))
 
 
@@ -745,10 +746,15 @@ def _fine_dofs(M: Amg) -> int:
 
 
 def vcycle_apply(M: Amg, r, z, nrhs=1, stream=None):
+    """z = M^-1 r.  FP64 vectors on any hierarchy; FP32 vectors (through vcycle_apply_ex)
+    on an F32 hierarchy."""
     n = _fine_dofs(M) * int(nrhs)
-    _dev_tensor(r, n, (F64,), "r")
-    _dev_tensor(z, n, (F64,), "z")
-    _check(_lib.vcycle_apply(M.h, _ptr(r), _ptr(z), nrhs, _stream(stream)), "vcycle_apply")
+    _dev_tensor(r, n, (F64, F32), "r")
+    _dev_tensor(z, n, (dtype_code(r),), "z")
+    if dtype_code(r) == F64:
+        _check(_lib.vcycle_apply(M.h, _ptr(r), _ptr(z), nrhs, _stream(stream)), "vcycle_apply")
+    else:
+        _check(_lib.vcycle_apply_ex(M.h, _ptr(r), _ptr(z), F32, nrhs, _stream(stream)), "vcycle_apply_ex")
 
 
 def pcg_solve(A: Bsr, M: Amg, b, x, rtol=1e-8, maxit=1000, nrhs=1, stream=None):

@@ -1908,6 +1908,25 @@ int amg_guard_status(amg_t M, int32_t* armed, int32_t* restarts) {
   BLK_API_END
 }
 
+int vcycle_apply_ex(amg_t M, const void* d_r, void* d_z, int vec_dtype, int32_t nrhs, void* stream) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(M != nullptr && d_r != nullptr && d_z != nullptr, BLKAMG_EINVAL, "NULL argument");
+  BLK_REQUIRE(vec_dtype == BLKAMG_F64 || vec_dtype == BLKAMG_F32, BLKAMG_EINVAL, "vec_dtype must be F64 or F32");
+  if (vec_dtype == BLKAMG_F64)
+    return vcycle_apply(M, static_cast<const double*>(d_r), static_cast<double*>(d_z), nrhs, stream);
+  BLK_REQUIRE(M->T == BLKAMG_F32, BLKAMG_EINVAL, "FP32 vectors need an F32 hierarchy");
+  BLK_REQUIRE(nrhs == 1 || nrhs == 8, BLKAMG_EINVAL, "vcycle_apply supports nrhs 1 or 8");
+  BLK_REQUIRE(d_r != d_z, BLKAMG_EINVAL, "r and z must not alias");
+  hipStream_t s = as_stream(stream);
+  ensure_vectors(M, nrhs);
+  if (M->guard_armed) mlp_check_levels(M, s);
+  const float* r = static_cast<const float*>(d_r);
+  float* z = static_cast<float*>(d_z);
+  if (nrhs == 1) vcycle_level<float, 1>(M, 0, r, z, s);
+  else vcycle_level<float, 8>(M, 0, r, z, s);
+  BLK_API_END
+}
+
 int vcycle_apply(amg_t M, const double* d_r, double* d_z, int32_t nrhs, void* stream) {
   BLK_API_BEGIN
   BLK_REQUIRE(M != nullptr && d_r != nullptr && d_z != nullptr, BLKAMG_EINVAL, "NULL argument");

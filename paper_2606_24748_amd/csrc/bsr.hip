@@ -420,7 +420,7 @@ int blkamg_set_allocator(blkamg_alloc_fn alloc_fn, blkamg_free_fn free_fn, void*
 }
 
 int bsr_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t nnzb, const int32_t* d_rowptr,
-               const int32_t* d_colidx, void* d_val, int dtype, bsr_t* out) {
+               const int32_t* d_colidx, void* d_val, int dtype, void* stream, bsr_t* out) {
   BLK_API_BEGIN
   BLK_REQUIRE(out != nullptr, BLKAMG_EINVAL, "out is NULL");
   *out = nullptr;
@@ -443,7 +443,10 @@ int bsr_create(int32_t nbr, int32_t nbc, int32_t bs_r, int32_t bs_c, int64_t nnz
   A->val = d_val;
   const char* v = std::getenv("BLKAMG_VALIDATE");
   if (v && v[0] == '1') {
-    ensure_host_pattern(A.get());
+    hipStream_t s = as_stream(stream);
+    A->h_rowptr = download(A->rowptr, static_cast<size_t>(nbr) + 1, s);
+    A->h_colidx = download(A->colidx, static_cast<size_t>(nnzb), s);
+    A->h_pattern = true;
     BLK_REQUIRE(A->h_rowptr[0] == 0 && A->h_rowptr[nbr] == nnzb, BLKAMG_EINVAL, "rowptr ends do not match nnzb");
     for (int32_t r = 0; r < nbr; ++r) {
       BLK_REQUIRE(A->h_rowptr[r] <= A->h_rowptr[r + 1], BLKAMG_EINVAL, "rowptr not monotone");

@@ -179,3 +179,27 @@ def test_symmetric_reads_give_identical_vcycle_and_pcg(hier):
     assert np.all(np.abs(out[0][0] - out[1][0]) <= tol * out[0][0])
     assert rel2(out[1][1].numpy(), out[0][1].numpy()) <= max(tol, 1e-14 if hier == B.F64 else 1e-9)
     assert rel2(out[1][2].numpy(), out[0][2].numpy()) <= 1e-9 and out[0][3] == out[1][3]
+
+
+@pytest.mark.parametrize("nrhs", [1, 8])
+def test_vcycle_on_fp32_vectors(nrhs):
+    """vcycle_apply_ex with FP32 vectors on an F32 hierarchy runs the same FP32 V-cycle
+    as the FP64 entry (which rounds its input to FP32 and widens the output): equal bit
+    for bit; FP32 vectors on an F64 hierarchy are refused."""
+    m, i, j, v, A = q1_problem(10, mat_seed=2)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    o = B.blkamg_opts_default()
+    o.hier_dtype, o.p_dtype = B.F32, B.F32
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    shape = (m.n_dof,) if nrhs == 1 else (m.n_dof, nrhs)
+    r = dev(np.random.default_rng(3).uniform(-1, 1, shape))
+    z64 = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    B.vcycle_apply(M, r, z64, nrhs=nrhs)
+    z32 = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    B.vcycle_apply(M, r.float().contiguous(), z32, nrhs=nrhs)
+    assert torch.equal(z32.double(), z64)
+    M64 = B.amg_setup(HA, m.coords, m.dirichlet)
+    with pytest.raises(B.BlkAmgError) as e:
+        B.vcycle_apply(M64, r.float().contiguous(), z32, nrhs=nrhs)
+    assert e.value.code == B.EINVAL
