@@ -114,6 +114,35 @@ def test_coo_plan_bit_exact_and_values():
         B.coo_plan_create(nbr, nbc, 3, 6, np.array([nbr], np.int32), np.array([0], np.int32))
 
 
+@pytest.mark.parametrize("br,bc", [(1, 1), (3, 3), (3, 6), (6, 6), (2, 2)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_coo_sum_every_block_shape(br, bc, fp32):
+    # each block size has its own sum kernel (one or three components per thread,
+    # or the generic loop): all keep the plan's stream order, so the bits match
+    nbr, nbc = 301, 177
+    i, j, v = synth.random_coo_stream(nbr, nbc, br, bc, 12000, seed=br * 10 + bc, neg_frac=0.1,
+                                      dup_pool=2500)
+    if fp32:
+        v = v.astype(np.float32)
+    plan, H = B.coo_plan_create(nbr, nbc, br, bc, i, j, val_dtype=B.F32 if fp32 else B.F64)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, H)
+    want = S.coo_assemble(nbr, nbc, i, j, v.astype(np.float64)).val
+    got = from_device_bsr(H).val
+    if fp32:
+        # the oracle sums in FP64; an FP32 sum of k terms is within k*eps of it
+        scale = S.coo_assemble(nbr, nbc, i, j, np.abs(v).astype(np.float64)).val
+        k = np.bincount(np.unique(i.astype(np.int64) * nbc + j, return_inverse=True)[1]).max()
+        assert np.all(np.abs(got - want) <= (k + 1) * np.finfo(np.float32).eps * scale)
+    else:
+        assert np.array_equal(got, want)
+    B.coo_assemble_blocked(plan, dev(v), B.ADD, H)
+    got2 = from_device_bsr(H).val
+    if fp32:
+        assert np.all(np.abs(got2 - 2 * want) <= 2 * (k + 2) * np.finfo(np.float32).eps * scale)
+    else:
+        assert np.array_equal(got2, want + want)
+
+
 @pytest.mark.parametrize("nbr,nbc,n,seed", [(257, 131, 20000, 4), (3000, 3000, 150000, 5), (1, 1, 50, 6)])
 def test_coo_device_plan_bit_exact(nbr, nbc, n, seed):
     """The plan built on the device from device coordinates: the same index map, segments
