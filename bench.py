@@ -44,14 +44,14 @@ if ROOT not in sys.path:
 
 METRIC = "PCG solve s + PtAP recompute s at 128^3 elasticity; %HBM peak; mixed vs FP64"
 
-# HBM traffic of the roofline kernel (fine 3x3 FP64 bsr_spmv at 128^3) from rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes, scaled by the copy-kernel calibration; valid only for
-# the kernel sources it was measured on (their SHA-256 below), else reported as null.
-# Summary and commands: profiles/bsr_spmv_fine_f64_128cube.md.
+# HBM traffic of the roofline kernel (fine 3x3 FP64 SpMV with symmetric reads at 128^3)
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the copy-kernel calibration;
+# valid only for the kernel sources it was measured on (their SHA-256 below), else
+# reported as null.  Summary and commands: profiles/bsr_spmv_fine_f64_128cube.md.
 TRAFFIC_RECORD = {
-    "sources_sha256": "580dd93f827400b9603b6cdfa1e31be4c60798ecefc42d2d946939dde98b508f",
-    "fetch_bytes": 4505270272,   # FETCH_SIZE 2,199,839 KiB x 2.00 (copy calibration)
-    "write_bytes": 52825088,     # WRITE_SIZE 51,587 KiB x 1.00
+    "sources_sha256": "ae8ed41ab6bc2c5296261528763c80eaed4d23113a0765d645cbde002ca6d96a",
+    "fetch_bytes": 3459045376,   # FETCH_SIZE 1,688,987 KiB x 2.00 (copy calibration)
+    "write_bytes": 53343232,     # WRITE_SIZE 52,093 KiB x 1.00
 }
 TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_amd/csrc/bsr.hip",
                    "paper_2606_24748_amd/csrc/common.hpp")
