@@ -5,15 +5,15 @@
 //
 // One 64-lane wave per element, lane 8a + b computes the 3x3 block K_ab.  Lanes 0..7
 // first evaluate the isoparametric Jacobian at Gauss point q = lane (J^-1 and the
-// weighted determinant go to LDS, 80 doubles per element); every lane then forms the
-// physical gradients of its two shape functions at each point from the LDS copy.
-// The block is then
+// weighted determinant go to LDS, 80 doubles per element).  The block is then
 //   * written to the blocked COO value stream (element-major, (a, b) order), which
-//     coo_assemble_blocked sums deterministically, or
+//     coo_assemble_blocked sums deterministically (fe_stream_kernel), or
 //   * added straight into the matrix at a slot precomputed on the host
-//     (element-by-element assembly), with hardware FP64 atomics, or in colour passes
-//     whose elements share no node, so that plain read-modify-writes cannot race and
-//     the summation order is fixed.
+//     (element-by-element assembly, fe_q1_kernel), with hardware FP64 atomics, or in
+//     colour passes whose elements share no node, so that plain read-modify-writes
+//     cannot race and the summation order is fixed.
+// Both kernels form every physical gradient with the same expression and sum the
+// Gauss points in the same order, so the two routes give the same block values.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -36,9 +36,9 @@ constexpr int kFeGeo = 10;   // per Gauss point: J^-1 (row-major) and det(J) / 8
 #ifndef BLK_FE_QUNROLL
 #define BLK_FE_QUNROLL 2
 #endif
-// Gauss points per loop trip.  Two keep the kernel at about 90 VGPRs (5 waves per SIMD
-// to cover the latency of the dependent node and coordinate loads) instead of ~130
-// (3 waves) fully unrolled; measured at 128^3: 3.48 ms (2 per trip), 3.56 (1), 3.70 (8).
+// Gauss points per loop trip of the element-by-element kernel.  Two keep it at about 90
+// VGPRs (5 waves per SIMD to cover the latency of the dependent node and coordinate
+// loads) instead of ~130 (3 waves) fully unrolled.
 constexpr int kFeQUnroll = BLK_FE_QUNROLL;
 
 enum FeMode { kStream = 0, kAtomic = 1, kPlain = 2 };
@@ -58,53 +58,142 @@ __device__ __forceinline__ double gauss_coord(int bit) {
   return bit ? 0.5 + h : 0.5 - h;
 }
 
+// Jacobian of the element at reference point (x, y, z): G[0..8] = J^-1 (row-major) and
+// G[9] = det(J) / 8, the Gauss weight of the 2x2x2 rule on [0, 1]^3 times det(J)
+__device__ __forceinline__ void jacobian_point(const int32_t* __restrict__ nodes, const double* __restrict__ coords,
+                                               double x, double y, double z, double* G) {
+  double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // J[r * 3 + k] = d x_r / d xi_k
+  for (int n = 0; n < 8; ++n) {
+    const double* X = coords + static_cast<int64_t>(nodes[n]) * 3;
+    double g[3];
+    ref_grad(n, x, y, z, g);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) J[r * 3 + k] += X[r] * g[k];
+  }
+  const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  const double r = 1.0 / det;
+  // inverse = adjugate / det, adjugate = transposed cofactor matrix
+  G[0] = c00 * r;
+  G[1] = (J[2] * J[7] - J[1] * J[8]) * r;
+  G[2] = (J[1] * J[5] - J[2] * J[4]) * r;
+  G[3] = c01 * r;
+  G[4] = (J[0] * J[8] - J[2] * J[6]) * r;
+  G[5] = (J[2] * J[3] - J[0] * J[5]) * r;
+  G[6] = c02 * r;
+  G[7] = (J[1] * J[6] - J[0] * J[7]) * r;
+  G[8] = (J[0] * J[4] - J[1] * J[3]) * r;
+  G[9] = det * 0.125;
+}
+
+// physical gradient: g_c = sum_k (dN/dxi_k) (J^-1)[k][c]
+__device__ __forceinline__ void phys_grad(const double rg[3], const double* G, double* g) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] = rg[0] * G[c] + rg[1] * G[3 + c] + rg[2] * G[6 + c];
+}
+
+// S += w det(J) g_a g_b^T at one point
+__device__ __forceinline__ void add_point(double wd, const double* ga, const double* gb, double S[9]) {
+  const double b0 = gb[0], b1 = gb[1], b2 = gb[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double wa = wd * ga[c];
+    S[c * 3 + 0] += wa * b0;
+    S[c * 3 + 1] += wa * b1;
+    S[c * 3 + 2] += wa * b2;
+  }
+}
+
+// lambda and mu are constant on the element, so with S = sum_q w det(J) g_a g_b^T the
+// block is  lambda S + mu (S^T + tr(S) I): one outer product per point
+__device__ __forceinline__ void element_block(double l, double m, const double S[9], double K[9]) {
+  const double mt = m * (S[0] + S[4] + S[8]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) K[c * 3 + d] = l * S[c * 3 + d] + m * S[d * 3 + c] + (c == d ? mt : 0.0);
+}
+
+// Each wave owns its element and its part of LDS, so a wave barrier orders the LDS
+// phases; no workgroup barrier couples the four waves.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stream mode.  After the Jacobians, lane 8n + q forms the physical gradient of shape
+// function n at Gauss point q once, so the per-block loop over the points only forms
+// outer products (about a third of the FP64 work of forming both gradients in every
+// lane).  One LDS buffer per wave holds the geometry and the gradients, then the 64
+// output blocks, which leave as one contiguous 4.6 KB run of 16-byte non-temporal
+// stores: the stream is read back only by the assembly, long after.
+// 128^3 distorted elements: 2.2 ms against 3.4 ms for the block-per-lane gradients
+// with workgroup barriers and plain stores.
+__global__ __launch_bounds__(256) void fe_stream_kernel(int64_t count, const int32_t* __restrict__ elem_nodes,
+                                                        const double* __restrict__ coords,
+                                                        const double* __restrict__ lam,
+                                                        const double* __restrict__ mu, double* __restrict__ out) {
+  constexpr int kGradOff = 8 * kFeGeo;  // geometry [8][kFeGeo], then gradients [q][n][3]
+  static_assert(kGradOff + 8 * 8 * 3 <= 64 * 9, "geometry and gradients fit in the block buffer");
+  __shared__ __align__(16) double buf[kFeWaves][64 * 9];
+  const int w = static_cast<int>(threadIdx.x) / 64, lane = static_cast<int>(threadIdx.x) % 64;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kFeWaves + w;
+  if (e >= count) return;
+  double* geo = buf[w];
+  double* grad = buf[w] + kGradOff;
+  if (lane < 8) {
+    const double x = gauss_coord(lane & 1), y = gauss_coord((lane >> 1) & 1), z = gauss_coord((lane >> 2) & 1);
+    jacobian_point(elem_nodes + e * 8, coords, x, y, z, geo + lane * kFeGeo);
+  }
+  wave_sync();
+  {
+    const int n = lane >> 3, q = lane & 7;
+    double rg[3];
+    ref_grad(n, gauss_coord(q & 1), gauss_coord((q >> 1) & 1), gauss_coord((q >> 2) & 1), rg);
+    phys_grad(rg, geo + q * kFeGeo, grad + (q * 8 + n) * 3);
+  }
+  wave_sync();
+  const int a = lane >> 3, b = lane & 7;
+  double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    add_point(geo[q * kFeGeo + 9], grad + (q * 8 + a) * 3, grad + (q * 8 + b) * 3, S);
+  double K[9];
+  element_block(lam[e], mu[e], S, K);
+  wave_sync();  // every lane has read the gradients before the blocks overwrite them
+#pragma unroll
+  for (int t = 0; t < 9; ++t) buf[w][lane * 9 + t] = K[t];
+  wave_sync();
+  using v2 = double __attribute__((ext_vector_type(2)));
+  const v2* src = reinterpret_cast<const v2*>(buf[w]);
+  v2* dst = reinterpret_cast<v2*>(out + e * 64 * 9);
+  for (int k = lane; k < 64 * 9 / 2; k += 64) __builtin_nontemporal_store(src[k], dst + k);
+}
+
+// Element-by-element modes: the same arithmetic, with each lane forming the gradients
+// of its own two shape functions at every point and adding its block at its slot.
 template <int kMode>
 __global__ __launch_bounds__(256) void fe_q1_kernel(int64_t count, const int32_t* __restrict__ order,
                                                     const int32_t* __restrict__ elem_nodes,
                                                     const double* __restrict__ coords, const double* __restrict__ lam,
                                                     const double* __restrict__ mu, const int32_t* __restrict__ slot,
                                                     double* __restrict__ out) {
+  static_assert(kMode == kAtomic || kMode == kPlain, "element-by-element modes only");
   __shared__ double geo[kFeWaves][8][kFeGeo];
-  // stream mode: the wave's 64 blocks, written out as one contiguous 4.6 KB run
-  __shared__ __align__(16) double kout[kMode == kStream ? kFeWaves : 1][kMode == kStream ? 64 * 9 : 2];
   const int w = static_cast<int>(threadIdx.x) / 64, lane = static_cast<int>(threadIdx.x) % 64;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * kFeWaves + w;
   const bool live = idx < count;
   const int64_t e = live ? (order ? order[idx] : idx) : 0;
   if (live && lane < 8) {
     const double x = gauss_coord(lane & 1), y = gauss_coord((lane >> 1) & 1), z = gauss_coord((lane >> 2) & 1);
-    double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // J[r * 3 + k] = d x_r / d xi_k
-    for (int n = 0; n < 8; ++n) {
-      const double* X = coords + static_cast<int64_t>(elem_nodes[e * 8 + n]) * 3;
-      double g[3];
-      ref_grad(n, x, y, z, g);
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) J[r * 3 + k] += X[r] * g[k];
-    }
-    const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
-    const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
-    const double r = 1.0 / det;
-    double* G = geo[w][lane];
-    // inverse = adjugate / det, adjugate = transposed cofactor matrix
-    G[0] = c00 * r;
-    G[1] = (J[2] * J[7] - J[1] * J[8]) * r;
-    G[2] = (J[1] * J[5] - J[2] * J[4]) * r;
-    G[3] = c01 * r;
-    G[4] = (J[0] * J[8] - J[2] * J[6]) * r;
-    G[5] = (J[2] * J[3] - J[0] * J[5]) * r;
-    G[6] = c02 * r;
-    G[7] = (J[1] * J[6] - J[0] * J[7]) * r;
-    G[8] = (J[0] * J[4] - J[1] * J[3]) * r;
-    G[9] = det * 0.125;
+    jacobian_point(elem_nodes + e * 8, coords, x, y, z, geo[w][lane]);
   }
   __syncthreads();
-  // waves past the end compute on unset geometry and store nothing; they stay to the
-  // end so that every wave reaches the second barrier of the stream mode
+  if (!live) return;
   const int a = lane >> 3, b = lane & 7;
-  // lambda and mu are constant on the element, so with S = sum_q w det(J) g_a g_b^T
-  // the block is  lambda S + mu (S^T + tr(S) I): one outer product per point
   double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll kFeQUnroll
   for (int q = 0; q < 8; ++q) {
@@ -113,45 +202,19 @@ __global__ __launch_bounds__(256) void fe_q1_kernel(int64_t count, const int32_t
     double ra[3], rb[3], ga[3], gb[3];
     ref_grad(a, x, y, z, ra);
     ref_grad(b, x, y, z, rb);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {  // physical gradient: g_c = sum_k (dN/dxi_k) (J^-1)[k][c]
-      ga[c] = ra[0] * G[c] + ra[1] * G[3 + c] + ra[2] * G[6 + c];
-      gb[c] = rb[0] * G[c] + rb[1] * G[3 + c] + rb[2] * G[6 + c];
-    }
-    const double wd = G[9];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double wa = wd * ga[c];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) S[c * 3 + d] += wa * gb[d];
-    }
+    phys_grad(ra, G, ga);
+    phys_grad(rb, G, gb);
+    add_point(G[9], ga, gb, S);
   }
-  const double l = lam[e], m = mu[e];
-  const double mt = m * (S[0] + S[4] + S[8]);
   double K[9];
+  element_block(lam[e], mu[e], S, K);
+  const int s = slot[e * 64 + lane];
+  if (s >= 0) {
+    double* o = out + static_cast<int64_t>(s) * 9;
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) K[c * 3 + d] = l * S[c * 3 + d] + m * S[d * 3 + c] + (c == d ? mt : 0.0);
-  if constexpr (kMode == kStream) {
-#pragma unroll
-    for (int t = 0; t < 9; ++t) kout[w][lane * 9 + t] = K[t];
-    __syncthreads();
-    if (live) {
-      const double2* src = reinterpret_cast<const double2*>(kout[w]);
-      double2* dst = reinterpret_cast<double2*>(out + e * 64 * 9);
-      for (int k = lane; k < 64 * 9 / 2; k += 64) dst[k] = src[k];
-    }
-  } else {
-    if (!live) return;
-    const int s = slot[e * 64 + lane];
-    if (s >= 0) {
-      double* o = out + static_cast<int64_t>(s) * 9;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        if constexpr (kMode == kAtomic) unsafeAtomicAdd(o + t, K[t]);
-        else o[t] += K[t];
-      }
+    for (int t = 0; t < 9; ++t) {
+      if constexpr (kMode == kAtomic) unsafeAtomicAdd(o + t, K[t]);
+      else o[t] += K[t];
     }
   }
 }
@@ -186,7 +249,10 @@ void launch_fe(int64_t count, const int32_t* order, const int32_t* elem_nodes, c
   if (count <= 0) return;
   const int64_t grid = grid_of(count);
   BLK_REQUIRE(grid <= INT32_MAX, BLKAMG_EINVAL, "too many elements for one launch");
-  fe_q1_kernel<kMode><<<static_cast<int>(grid), 256, 0, s>>>(count, order, elem_nodes, coords, lam, mu, slot, out);
+  if constexpr (kMode == kStream)
+    fe_stream_kernel<<<static_cast<int>(grid), 256, 0, s>>>(count, elem_nodes, coords, lam, mu, out);
+  else
+    fe_q1_kernel<kMode><<<static_cast<int>(grid), 256, 0, s>>>(count, order, elem_nodes, coords, lam, mu, slot, out);
   HIP_CHECK(hipGetLastError());
 }
 
