@@ -96,13 +96,17 @@ int lanes_for(const bsr_s* A, int nrhs) {
   if (const int t = A->tuned[nrhs > 1 ? 1 : 0]) return t;
   const double avg = A->avg_blocks_per_row();
   const size_t vb = A->block_elems() * dtype_size(A->dtype);  // bytes per block
-  int G;
-  if (avg <= 8.0) G = 8;
-  else if (avg <= 16.0) G = 16;
-  else if (avg <= 40.0) G = 32;
-  else G = 64;
-  (void)vb;  // measured at 128^3: one block per lane beats two for both F32 and F64
-  return G * 8 + 1;
+  // Measured on the 128^3 hierarchy.  Fine 3x3 operator (27 blocks per row): 32 lanes,
+  // one block per lane, for both F32 and F64.  6x6 F64 blocks (288 bytes) want two
+  // blocks per lane and fewer lanes (level-1 operator, 26 per row: 16 x 2 112 us against
+  // 188 us with 32 x 1; its prolongator, 4.5 per row: 8 x 2 21 against 32 us).  Long
+  // rows (the restrictions, 106-121 blocks per row) take 64 x 2 (0.289 against 0.304 ms
+  // for the fine 6x3 F64 one; 20 against 40 us for the level-1 6x6 one).
+  const bool big = vb >= 288;
+  if (avg <= 8.0) return lane_code(8, big ? 2 : 1);
+  if (avg <= 16.0) return lane_code(16, 1);
+  if (avg <= 40.0) return big ? lane_code(16, 2) : lane_code(32, 1);
+  return lane_code(64, 2);
 }
 
 namespace {
@@ -328,8 +332,12 @@ const int32_t* symmetric_mirror(bsr_s* A, hipStream_t s) {
 int lanes_for_reads(const bsr_s* A, int nrhs, const int32_t* mir) {
   // symmetric reads of 3x3 blocks: 16 lanes per row, two blocks per lane and step
   // (measured on the fine FP64 operator at 128^3: 0.768 ms against 0.79-0.83 ms with
-  // 32 x 1, 32 x 2, 8 x 1-2 and 1.1 ms with 64 lanes)
-  if (mir && nrhs == 1 && A->br == 3 && A->tuned[0] == 0) return lane_code(16, 2);
+  // 32 x 1, 32 x 2, 8 x 1-2 and 1.1 ms with 64 lanes); of 6x6 F64 blocks: 8 x 2
+  // (level-1 operator at 128^3: 94 us against 98 with 16 x 2 and 126 with 32 x 1)
+  if (mir && nrhs == 1 && A->tuned[0] == 0) {
+    if (A->br == 3) return lane_code(16, 2);
+    if (A->block_elems() * dtype_size(A->dtype) >= 288) return lane_code(8, 2);
+  }
   return lanes_for(A, nrhs);
 }
 
