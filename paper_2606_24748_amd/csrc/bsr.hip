@@ -100,13 +100,15 @@ int lanes_for(const bsr_s* A, int nrhs) {
   // one block per lane, for both F32 and F64.  6x6 F64 blocks (288 bytes) want two
   // blocks per lane and fewer lanes (level-1 operator, 26 per row: 16 x 2 112 us against
   // 188 us with 32 x 1; its prolongator, 4.5 per row: 8 x 2 21 against 32 us).  Long
-  // rows (the restrictions, 106-121 blocks per row) take 64 x 2 (0.289 against 0.304 ms
-  // for the fine 6x3 F64 one; 20 against 40 us for the level-1 6x6 one).
+  // rows of the restrictions' 6x3 and 6x6 blocks (106-121 per row) take 64 x 2 (0.289
+  // against 0.304 ms for the fine F64 one, 0.153 against 0.158 ms in F32; 20 against
+  // 40 us for the level-1 F64 one); long rows of 3x3 blocks (the triquadratic fine
+  // operator, 62 per row) keep one block per lane.
   const bool big = vb >= 288;
   if (avg <= 8.0) return lane_code(8, big ? 2 : 1);
   if (avg <= 16.0) return lane_code(16, 1);
   if (avg <= 40.0) return big ? lane_code(16, 2) : lane_code(32, 1);
-  return lane_code(64, 2);
+  return lane_code(64, A->block_elems() >= 18 ? 2 : 1);
 }
 
 namespace {
