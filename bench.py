@@ -49,9 +49,9 @@ METRIC = "PCG solve s + PtAP recompute s at 128^3 elasticity; %HBM peak; mixed v
 # valid only for the kernel sources it was measured on (their SHA-256 below), else
 # reported as null.  Summary and commands: profiles/bsr_spmv_fine_f64_128cube.md.
 TRAFFIC_RECORD = {
-    "sources_sha256": "ae8ed41ab6bc2c5296261528763c80eaed4d23113a0765d645cbde002ca6d96a",
-    "fetch_bytes": 3459045376,   # FETCH_SIZE 1,688,987 KiB x 2.00 (copy calibration)
-    "write_bytes": 53343232,     # WRITE_SIZE 52,093 KiB x 1.00
+    "sources_sha256": "892a7e82017996abe7144defdae117382aaddce8e76006c65a23a7a555f27c00",
+    "fetch_bytes": 3458992128,   # FETCH_SIZE 1,688,961 KiB x 2.00 (copy calibration)
+    "write_bytes": 53366784,     # WRITE_SIZE 52,116 KiB x 1.00
 }
 TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_amd/csrc/bsr.hip",
                    "paper_2606_24748_amd/csrc/common.hpp")
