@@ -261,7 +261,8 @@ int coo_assemble_blocked(coo_plan_t plan, const void* d_vals, int val_dtype, int
 /* Element blocks as a blocked COO value stream: d_out double [n_elem*64 + n_identity]
  * [3][3], element-major with block 64e + 8a + b = K_ab of element e, followed by
  * n_identity identity blocks (e.g. the Dirichlet diagonal of a clamped mesh).  Feed it
- * to coo_assemble_blocked with the matching coordinates.  Async, no allocation. */
+ * to coo_assemble_blocked with the matching coordinates.  d_out must be 16-byte aligned
+ * when n_elem > 0 (EINVAL otherwise).  Async, no allocation. */
 int fe_q1_stream(int64_t n_elem, const int32_t* d_elem_nodes, const double* d_coords,
                  const double* d_lam, const double* d_mu, int64_t n_identity,
                  double* d_out, void* stream);

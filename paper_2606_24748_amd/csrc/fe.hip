@@ -276,6 +276,8 @@ int fe_q1_stream(int64_t n_elem, const int32_t* d_elem_nodes, const double* d_co
   BLK_REQUIRE(n_elem >= 0 && n_identity >= 0, BLKAMG_EINVAL, "negative size");
   BLK_REQUIRE(d_out != nullptr || n_elem + n_identity == 0, BLKAMG_EINVAL, "d_out is NULL");
   BLK_REQUIRE(n_elem == 0 || (d_elem_nodes && d_coords && d_lam && d_mu), BLKAMG_EINVAL, "NULL element input");
+  BLK_REQUIRE(n_elem == 0 || reinterpret_cast<uintptr_t>(d_out) % 16 == 0, BLKAMG_EINVAL,
+              "d_out must be 16-byte aligned (the element blocks leave in 16-byte stores)");
   hipStream_t s = as_stream(stream);
   launch_fe<kStream>(n_elem, nullptr, d_elem_nodes, d_coords, d_lam, d_mu, nullptr, d_out, s);
   if (n_identity > 0) {

@@ -115,6 +115,11 @@ def test_fe_plan_errors():
     with pytest.raises(ValueError):
         B.fe_q1_stream(torch.as_tensor(bad).cuda().int(), d["X"], d["lam"], d["mu"],
                        torch.empty(m.n_elem * 64 * 9, dtype=torch.float64, device="cuda"))
+    # the stream kernel stores 16 bytes at a time: an output 8 bytes off alignment is
+    # refused before any launch
+    buf = torch.empty(m.n_elem * 64 * 9 + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BlkAmgError):
+        B.fe_q1_stream(d["en"], d["X"], d["lam"], d["mu"], buf[1:])
 
 
 def test_fe_empty_inputs():
