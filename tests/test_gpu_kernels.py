@@ -365,6 +365,38 @@ def test_spmv_sym_on_the_elasticity_operator_and_refusals():
         B.bsr_spmv_sym(HU, 1.0, dev(np.zeros(9)), 0.0, torch.zeros(9, dtype=torch.float64, device="cuda"))
 
 
+def test_spmv_sym_follows_the_values():
+    """The symmetric reads see the current values: after the library changes them (COO
+    assembly) and after the caller writes them (declared with bsr_mark_modified); a
+    pattern whose mirror search fails on a row listed out of order is refused."""
+    m, i, j, v, A = q1_problem(6, mat_seed=5)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    x = dev(np.random.default_rng(11).uniform(-1, 1, A.nbr * 3))
+    y = torch.zeros(A.nbr * 3, dtype=torch.float64, device="cuda")
+    for scale in (1.0, 2.5):
+        B.coo_assemble_blocked(plan, dev(v * scale), B.INSERT, HA)
+        B.bsr_spmv_sym(HA, 1.0, x, 0.0, y)
+        assert rel2(y.cpu().numpy(), scale * S.spmv(A, x.cpu().numpy())) <= 1e-14, scale
+    # a matrix over caller arrays, its values then changed by the caller
+    rpt = torch.as_tensor(A.rowptr.astype(np.int32), device="cuda")
+    cit = torch.as_tensor(A.colidx.astype(np.int32), device="cuda")
+    vt = torch.as_tensor(A.val.reshape(-1).copy(), device="cuda")
+    HB = B.bsr_create(A.nbr, A.nbc, 3, 3, rpt, cit, vt)
+    B.bsr_spmv_sym(HB, 1.0, x, 0.0, y)
+    assert rel2(y.cpu().numpy(), S.spmv(A, x.cpu().numpy())) <= 1e-14
+    vt.mul_(-3.0)
+    B.bsr_mark_modified(HB)
+    B.bsr_spmv_sym(HB, 1.0, x, 0.0, y)
+    assert rel2(y.cpu().numpy(), -3.0 * S.spmv(A, x.cpu().numpy())) <= 1e-14
+    # symmetric pattern, but row 1 lists its columns out of order
+    rp = torch.tensor([0, 2, 4, 6], dtype=torch.int32, device="cuda")
+    ci = torch.tensor([0, 1, 1, 0, 1, 2], dtype=torch.int32, device="cuda")
+    vv = torch.ones(6 * 9, dtype=torch.float64, device="cuda")
+    HU = B.bsr_create(3, 3, 3, 3, rp, ci, vv)
+    with pytest.raises(B.BlkAmgError):
+        B.bsr_spmv_sym(HU, 1.0, dev(np.zeros(9)), 0.0, torch.zeros(9, dtype=torch.float64, device="cuda"))
+
+
 @pytest.mark.parametrize("case", ["q1_sym", "q1_full", "rand6_sym", "rand3_empty_rows", "f32_sym", "c_sort_nostage",
                                   "q2_long_rows_sym", "q2_long_rows_full"])
 def test_ptap_device_symbolic_equals_host_build(case, monkeypatch):
