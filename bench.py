@@ -56,19 +56,29 @@ TRAFFIC_RECORD = {
 TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_amd/csrc/bsr.hip",
                    "paper_2606_24748_amd/csrc/common.hpp")
 
+# HBM traffic of one Galerkin recompute over all levels (FP64 hierarchy at 128^3: the
+# six pair-list passes), from the same kind of counter passes; null once its sources
+# change.  Summary: profiles/ptap_counters_128cube.md.
+PTAP_TRAFFIC_RECORD = {
+    "sources_sha256": "3c22be9a5a0388116bcf0146961612bb8443321bbf67b3055750176c0e2bee30",
+    "fetch_bytes": 34556499968,  # FETCH_SIZE 16,873,291 KiB x 2.00
+    "write_bytes": 5250577408,   # WRITE_SIZE 5,127,517 KiB x 1.00
+}
+PTAP_TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/ptap.hip", "paper_2606_24748_amd/csrc/ptap_plan.hpp",
+                        "paper_2606_24748_amd/csrc/ptap_symbolic.hip", "paper_2606_24748_amd/csrc/common.hpp")
 
-def kernel_sources_sha256() -> str:
+
+def kernel_sources_sha256(sources=TRAFFIC_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    rec = TRAFFIC_RECORD
-    if not rec or rec.get("sources_sha256") != kernel_sources_sha256():
+def measured_traffic(rec=TRAFFIC_RECORD, sources=TRAFFIC_SOURCES):
+    if not rec or rec.get("sources_sha256") != kernel_sources_sha256(sources):
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
@@ -751,14 +761,16 @@ def run_ptap_only(args, B, RL, torch, dev, stream):
     return {"variant": var, "n": n, "ptap_ms": ms, "median_ms": statistics.median(ms) if ms else None}
 
 
-def _ptap_roofline(RL, r):
+def _ptap_roofline(RL, r, fp64=False):
     """Galerkin recompute over all levels against the HBM roofline: the algorithmic bytes
     of the recompute (A and P read once, A_c written once, int32 indices; no cast of the
-    fine operator) over the median recompute time."""
+    fine operator) over the median recompute time; traffic from the recorded counters
+    (FP64 hierarchy only)."""
     ms = r["median_ms"]["ptap_ms"]
     ach = r["ptap_alg_bytes"] / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / RL.HBM_PEAK_GBS,
-            "traffic": None, "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
+            "traffic": measured_traffic(PTAP_TRAFFIC_RECORD, PTAP_TRAFFIC_SOURCES) if fp64 else None,
+            "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
             "median_ms": ms}
 
 
@@ -908,7 +920,7 @@ def main(argv=None):
                      "own_min_frac": psym["achieved_GBs"] / RL.HBM_PEAK_GBS,
                      "full_reads": {"avg_launch_ms": pfull["avg_launch_ms"], "bytes_per_launch": pfull["bytes_per_launch"],
                                     "frac": pfull["achieved_GBs"] / RL.HBM_PEAK_GBS}},
-        "ptap_roofline": _ptap_roofline(RL, hr),
+        "ptap_roofline": _ptap_roofline(RL, hr, fp64=head == "fp64"),
         "copy_GBs": copy["GBs"],
         "coo_plan_ms": {"host": 1e3 * t_plan, "device": 1e3 * plan_dev["device_s"]},
         "cold_setup_s": {"device": cold_setup["device_s"], "host_symbolic": cold_setup["host_symbolic_s"]},
