@@ -182,3 +182,30 @@ def test_fullsize_ptap_sampled_blocks_match_oracle(big):
         print(f"level {l + 1}: {len(picks)} sampled blocks, worst {worst:.2e}, Frobenius {frob:.2e}", flush=True)
         assert frob <= 1e-12
         del A, P, Ac
+
+
+def test_fullsize_fe_stream_sampled_elements_match_oracle():
+    """The element kernel at the size the FE benchmark times: 2,097,152 distorted
+    trilinear elements (interior nodes moved by up to 0.2 h, seed 31), 9.7 GB of
+    blocks; sampled elements, the first and the last, against the oracle's element
+    matrix, and the identity tail."""
+    from oracle import fe
+    print(f"full-size FE stream n={N}", flush=True)
+    m = synth.make_mesh(N, distort=0.2, seed=31)
+    lam, mu = synth.lame(*synth.materials(m.n_elem, 11))
+    en = torch.as_tensor(m.elem_nodes.astype(np.int32), device="cuda")
+    X = torch.as_tensor(m.coords, device="cuda")
+    out = torch.empty((m.n_elem * 64 + m.n_dirichlet, 3, 3), dtype=torch.float64, device="cuda")
+    B.fe_q1_stream(en, X, torch.as_tensor(lam, device="cuda"), torch.as_tensor(mu, device="cuda"), out,
+                   n_identity=m.n_dirichlet)
+    rng = np.random.default_rng(5)
+    elems = np.unique(np.concatenate([rng.integers(0, m.n_elem, 200), [0, 1, m.n_elem - 2, m.n_elem - 1]]))
+    idx = torch.as_tensor((elems[:, None] * 64 + np.arange(64)[None, :]).reshape(-1), device="cuda")
+    got = out[idx].cpu().numpy().reshape(len(elems), 64, 3, 3)
+    for t, e in enumerate(elems):
+        want = fe.element_blocks(m.coords[m.elem_nodes[e]], lam[e], mu[e]).reshape(64, 3, 3)
+        assert np.abs(got[t] - want).max() <= 1e-13 * np.abs(want).max(), e
+    tail = out[m.n_elem * 64:].cpu().numpy()
+    assert np.array_equal(tail, np.broadcast_to(np.eye(3), (m.n_dirichlet, 3, 3)))
+    del out
+    torch.cuda.empty_cache()
