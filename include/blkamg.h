@@ -337,7 +337,10 @@ typedef struct {
                                every smoothed level is refreshed by Lanczos (all flagged as
                                fallback) and the solve restarts from x = 0.  vcycle_apply
                                and the other solves first run the deferred smoother test.
-                               The cold setup always runs the smoother test. */
+                               With one instance the cold setup then also takes the
+                               network's lambda_hat and omega without the smoother test
+                               (omega only shapes the coarse space; the first solve checks
+                               the smoother); with several it runs the test. */
   int32_t sym_spmv;         /* 1 (default): the hierarchy's SpMVs on FP64 level operators
                                (smoother, residual, Lanczos, growth test) and pcg_solve's
                                A p read only the diagonal and upper blocks of a

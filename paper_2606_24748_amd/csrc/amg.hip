@@ -929,7 +929,10 @@ void mlp_refresh(amg_s* M, hipStream_t s) {
 // segment, into omega_seg): with a model and eig_mode MLP, the network's lambda_hat
 // (Chebyshev bounds) and omega (prolongator smoothing), kept when every segment's
 // smoother passes the growth test; otherwise, or without a model, Lanczos and
-// omega = omega_scale / lambda_hat.  Records both in M->setup_*.  Sync.
+// omega = omega_scale / lambda_hat.  Under the deferred guard (GUARD_PCG, one
+// instance) no growth test runs here either: CG checks the smoother scalars, and the
+// prolongator weight only shapes the coarse space (any finite positive omega leaves
+// the Galerkin operator SPD).  Records both in M->setup_*.  Sync.
 void setup_level_scalars(amg_s* M, int l, std::vector<double>& omega_seg, hipStream_t s) {
   Level& L = *M->lv[l];
   const int na = L.n_act;
@@ -951,12 +954,14 @@ void setup_level_scalars(amg_s* M, int l, std::vector<double>& omega_seg, hipStr
     level_features(M, l, M->feat.p, s);
     mlp_predict(M, na, s);
     refresh_level_scalars(M, l, M->pred_lam.p, s);
-    growth_level(M, l, s);
+    const bool deferred = M->o.mlp_guard == BLKAMG_GUARD_PCG && M->n_inst == 1;
+    if (!deferred) growth_level(M, l, s);
     std::vector<LevelScalars> q = download(scl, static_cast<size_t>(na), s);
     om = download(M->pred_omega.p, static_cast<size_t>(na), s);
     learned = true;
     for (int t = 0; t < na; ++t)
-      learned = learned && !growth_fails(q[t], nullptr) && om[t] > 0.0 && std::isfinite(om[t]);
+      learned = learned && (deferred || !growth_fails(q[t], nullptr)) && om[t] > 0.0 && std::isfinite(om[t]) &&
+                q[t].lam > 0.0 && std::isfinite(q[t].lam);
   }
   if (!learned) refresh_level_scalars(M, l, nullptr, s);
   std::vector<LevelScalars> q = download(scl, static_cast<size_t>(na), s);

@@ -260,6 +260,38 @@ def test_deferred_guard_keeps_a_good_bound_and_checks_other_solves():
     del it_l
 
 
+def test_deferred_guard_covers_the_cold_setup():
+    """GUARD_PCG with the model given from the cold setup on: the setup keeps the
+    network's lambda_hat and omega without a smoother test of its own, even a far too
+    low bound, and arms the guard; the first CG sees the failing smoother, refreshes by
+    Lanczos and restarts, and converges.  With GUARD_SMOOTHER the setup's test rejects
+    the same model."""
+    m = synth.make_mesh(10)
+    i, j = synth.coo_indices(m)
+    v = synth.coo_values(m, *synth.lame(*synth.materials(m.n_elem, 6)))
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    M0 = B.amg_setup(HA, m.coords, m.dirichlet)
+    lam_true = B.amg_judge_lambdas(M0, 50)[:, 0]
+    bad = _const_model(0.1 * lam_true[0], omega=4.0 / (3.0 * lam_true[0]))
+    b = dev(synth.rhs(m, 2))
+    for guard in (B.GUARD_PCG, B.GUARD_SMOOTHER):
+        o = B.blkamg_opts_default()
+        o.eig_mode, o.mlp_guard = B.EIG_MLP, guard
+        keep = B.opts_with_model(o, bad)
+        M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+        del keep
+        _, om, learned = B.amg_setup_weights(M)
+        if guard == B.GUARD_PCG:
+            assert learned.all() and np.allclose(om[:, 0], 4.0 / (3.0 * lam_true[0]), rtol=1e-5)
+            assert B.amg_guard_status(M) == (True, 0)
+            x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+            code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+            assert code == B.OK and rel <= 1e-8 and B.amg_guard_status(M) == (False, 1)
+        else:
+            assert not learned.any()
+
+
 def test_model_validation_and_missing_model():
     m, A, plan, HA, M = _q1_gpu(6, 6, eig=B.EIG_MLP)
     bad = _const_model(2.0)
