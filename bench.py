@@ -60,9 +60,9 @@ TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/spmv_core.hpp", "paper_2606_24748_
 # six pair-list passes), from the same kind of counter passes; null once its sources
 # change.  Summary: profiles/ptap_counters_128cube.md.
 PTAP_TRAFFIC_RECORD = {
-    "sources_sha256": "3c22be9a5a0388116bcf0146961612bb8443321bbf67b3055750176c0e2bee30",
-    "fetch_bytes": 34556499968,  # FETCH_SIZE 16,873,291 KiB x 2.00
-    "write_bytes": 5250577408,   # WRITE_SIZE 5,127,517 KiB x 1.00
+    "sources_sha256": "ad6696f0fa84ed15d7f74fa1396c3ee4378b199e4a69acbec0839a739ff6b56a",
+    "fetch_bytes": 34558126080,  # FETCH_SIZE 16,874,085 KiB x 2.00
+    "write_bytes": 5251006464,   # WRITE_SIZE 5,127,936 KiB x 1.00
 }
 PTAP_TRAFFIC_SOURCES = ("paper_2606_24748_amd/csrc/ptap.hip", "paper_2606_24748_amd/csrc/ptap_plan.hpp",
                         "paper_2606_24748_amd/csrc/ptap_symbolic.hip", "paper_2606_24748_amd/csrc/common.hpp")
@@ -694,9 +694,15 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
     vsz = 8 if o.hier_dtype == B.F64 else 4
     psz = {B.F64: 8, B.F32: 4, B.BF16: 2}[o.p_dtype]
     ptap_bytes = 0
+    ptap_flops = 0  # the products the recompute executes (its plans' pair counts)
     for l in range(nl - 1):
         d, c = lev[l], lev[l + 1]
         ptap_bytes += RL.ptap_bytes(d["nbr"], d["nnzb"], d["bs"], d["p_nnzb"], 6, c["nbr"], c["nnzb"], vsz, psz)
+        pi = B.ptap_plan_info(M.level(l + 1)[0])
+        if ptap_flops is not None and pi["ap_pairs"] >= 0 and pi["c_pairs"] >= 0:
+            ptap_flops += RL.ptap_flops(pi["ap_pairs"], pi["c_pairs"], d["bs"], 6)
+        else:
+            ptap_flops = None
     res = {
         "setup_s": t_setup, "levels": lev, "steps": rec, "median_ms": med,
         "pcg_plus_ptap_s": (med["pcg_ms"] + med["ptap_ms"]) / 1e3,
@@ -704,6 +710,7 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
         "iterations": [rr["its"] for rr in rec], "true_relres": true_rel,
         "ptap_alg_GBs": ptap_bytes / (med["ptap_ms"] * 1e-3) / 1e9,
         "ptap_alg_bytes": ptap_bytes,
+        "ptap_flops": ptap_flops,
         "x_norm": float(torch.linalg.norm(x)),
     }
     res["_x"] = x
@@ -772,13 +779,20 @@ def _ptap_roofline(RL, r, fp64=False):
     """Galerkin recompute over all levels against the HBM roofline: the algorithmic bytes
     of the recompute (A and P read once, A_c written once, int32 indices; no cast of the
     fine operator) over the median recompute time; traffic from the recorded counters
-    (FP64 hierarchy only)."""
+    (FP64 hierarchy only).  Beside it the vector-ALU bound: the block products the
+    plans execute (2 bs bs 6 flops per A P pair, 2 6 bs 6 per R (A P) pair) against the
+    FP64 (or FP32) vector peak."""
     ms = r["median_ms"]["ptap_ms"]
     ach = r["ptap_alg_bytes"] / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / RL.HBM_PEAK_GBS,
-            "traffic": measured_traffic(PTAP_TRAFFIC_RECORD, PTAP_TRAFFIC_SOURCES) if fp64 else None,
-            "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
-            "median_ms": ms}
+    out = {"bound": "hbm", "achieved": ach, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / RL.HBM_PEAK_GBS,
+           "traffic": measured_traffic(PTAP_TRAFFIC_RECORD, PTAP_TRAFFIC_SOURCES) if fp64 else None,
+           "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
+           "median_ms": ms}
+    if r.get("ptap_flops"):
+        tf = r["ptap_flops"] / (ms * 1e-3) / 1e12
+        pk = RL.FP64_PEAK_TFLOPS if fp64 else RL.FP32_PEAK_TFLOPS
+        out["valu"] = {"flops": r["ptap_flops"], "achieved": tf, "peak": pk, "unit": "TFLOP/s", "frac": tf / pk}
+    return out
 
 
 def main(argv=None):

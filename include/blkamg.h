@@ -205,6 +205,13 @@ int ptap_symbolic_ex(bsr_t A, bsr_t P, int flags, bsr_t* C, void* stream);
  * ESTATE.  C must come from ptap_symbolic(A, P).  No allocation, no host
  * synchronisation.  Async. */
 int ptap_numeric(bsr_t A, bsr_t P, bsr_t C, void* stream);
+/* Sizes of the numeric plan that ptap_symbolic attached to C (paper §3.5), for the
+ * flop count of a recompute: *ap_nnzb blocks of A P, *ap_pairs (A block, P block)
+ * products of the A P pass and *c_pairs (P^T block, A P block) products of the
+ * R (A P) pass (the upper blocks' only when *symmetric).  The pair counts are -1 when
+ * the plan holds no contribution lists.  Any output may be NULL.  EINVAL if C carries
+ * no plan.  Sync (reads two counts from the device). */
+int ptap_plan_info(bsr_t C, int64_t* ap_nnzb, int64_t* ap_pairs, int64_t* c_pairs, int32_t* symmetric);
 
 /* ==========================================================================
  * Blocked COO assembly (paper §3.4 and §5)

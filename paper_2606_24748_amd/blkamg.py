@@ -85,6 +85,7 @@ _SIG = {
     "ptap_symbolic": (C.c_int, [_p, _p, C.POINTER(_p), _p]),
     "ptap_symbolic_ex": (C.c_int, [_p, _p, C.c_int, C.POINTER(_p), _p]),
     "ptap_numeric": (C.c_int, [_p, _p, _p, _p]),
+    "ptap_plan_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32)]),
     "coo_plan_create": (C.c_int, [_i32, _i32, _i32, _i32, _i64, _p, _p, C.c_int, C.c_int, C.POINTER(_p),
                                   C.POINTER(_p), _p]),
     "coo_plan_destroy": (C.c_int, [_p]),
@@ -338,6 +339,14 @@ def ptap_symbolic_ex(A: Bsr, P: Bsr, flags: int, stream=None) -> Bsr:
 
 def ptap_numeric(A: Bsr, P: Bsr, Cm: Bsr, stream=None):
     _check(_lib.ptap_numeric(A.h, P.h, Cm.h, _stream(stream)), "ptap_numeric")
+
+
+def ptap_plan_info(Cm: Bsr) -> dict:
+    """Sizes of the Galerkin plan attached to Cm: blocks of A P, the A P pass's and the
+    R (A P) pass's block products (-1 without contribution lists), symmetric mode."""
+    ap, pa, pc, sym = _i64(), _i64(), _i64(), _i32()
+    _check(_lib.ptap_plan_info(Cm.h, C.byref(ap), C.byref(pa), C.byref(pc), C.byref(sym)), "ptap_plan_info")
+    return {"ap_nnzb": ap.value, "ap_pairs": pa.value, "c_pairs": pc.value, "symmetric": bool(sym.value)}
 
 
 class CooPlan:

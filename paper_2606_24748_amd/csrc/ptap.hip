@@ -871,4 +871,22 @@ int ptap_numeric(bsr_t A, bsr_t P, bsr_t C, void* stream) {
   BLK_API_END
 }
 
+int ptap_plan_info(bsr_t C, int64_t* ap_nnzb, int64_t* ap_pairs, int64_t* c_pairs, int32_t* symmetric) {
+  BLK_API_BEGIN
+  BLK_REQUIRE(C != nullptr, BLKAMG_EINVAL, "C is NULL");
+  auto* pl = static_cast<PtapPlan*>(C->ext.get());
+  BLK_REQUIRE(pl != nullptr, BLKAMG_EINVAL, "C was not created by ptap_symbolic");
+  auto total = [](const PairList& L) -> int64_t {
+    if (L.width == 0 || L.ptr.n == 0) return -1;
+    int32_t v = 0;
+    HIP_CHECK(hipMemcpy(&v, L.ptr.p + (L.ptr.n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    return v;
+  };
+  if (ap_nnzb) *ap_nnzb = pl->ap_nslots;
+  if (ap_pairs) *ap_pairs = total(pl->ap_pairs);
+  if (c_pairs) *c_pairs = total(pl->c_pairs);
+  if (symmetric) *symmetric = pl->sym ? 1 : 0;
+  BLK_API_END
+}
+
 }  // extern "C"

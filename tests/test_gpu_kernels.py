@@ -211,6 +211,18 @@ def test_ptap_random_against_oracle_and_stamp_gating():
     first = from_device_bsr(HC).val.copy()
     B.ptap_numeric(HA, HP, HC)
     assert np.array_equal(from_device_bsr(HC).val, first)
+    # the plan's sizes: the A P pattern and the block products of both passes, counted
+    # from the oracle's patterns
+    pl = np.diff(P.rowptr)
+    ap_len = np.array([len(np.unique(np.concatenate([P.colidx[P.rowptr[k]:P.rowptr[k + 1]]
+                                                     for k in A.colidx[A.rowptr[r]:A.rowptr[r + 1]]])))
+                       for r in range(A.nbr)])
+    info = B.ptap_plan_info(HC)
+    assert info["ap_nnzb"] == ap_len.sum() and not info["symmetric"]
+    assert info["ap_pairs"] == pl[A.colidx].sum()
+    assert info["c_pairs"] == (pl * ap_len).sum()
+    with pytest.raises(B.BlkAmgError):
+        B.ptap_plan_info(HA)
 
 
 def test_ptap_coarse_6x6_and_f32():
