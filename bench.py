@@ -711,6 +711,7 @@ def run_variant(args, B, RL, torch, dev, stream, var, mesh, plan, HA, a_inf, val
         "ptap_alg_GBs": ptap_bytes / (med["ptap_ms"] * 1e-3) / 1e9,
         "ptap_alg_bytes": ptap_bytes,
         "ptap_flops": ptap_flops,
+        "pcg_iter_bytes": RL.pcg_iteration_bytes(lev, vsz, psz),
         "x_norm": float(torch.linalg.norm(x)),
     }
     res["_x"] = x
@@ -773,6 +774,16 @@ def run_ptap_only(args, B, RL, torch, dev, stream):
             ms.append(e0.elapsed_time(e1))
         log(f"[ptap/{var}] step {s}: {e0.elapsed_time(e1):.3f} ms")
     return {"variant": var, "n": n, "ptap_ms": ms, "median_ms": statistics.median(ms) if ms else None}
+
+
+def _pcg_roofline(RL, r):
+    """PCG over the median timed solve: iterations x the iteration byte model."""
+    its = [rr["its"] for rr in r["steps"]]
+    ms = [rr["pcg_ms"] for rr in r["steps"]]
+    per = [r["pcg_iter_bytes"] * i / (t * 1e-3) / 1e9 for i, t in zip(its, ms)]
+    ach = statistics.median(per)
+    return {"bound": "hbm", "achieved": ach, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / RL.HBM_PEAK_GBS,
+            "bytes_per_iteration": r["pcg_iter_bytes"], "iterations": statistics.median(its)}
 
 
 def _ptap_roofline(RL, r, fp64=False):
@@ -932,6 +943,11 @@ def main(argv=None):
                    "n": n, "dofs": mesh.n_dof, "variant": head},
         "pcg_ms": hr["median_ms"]["pcg_ms"], "ptap_ms": hr["median_ms"]["ptap_ms"],
         "pcg_its": statistics.median(hr["iterations"]),
+        "pcg_ms_range": [min(rr["pcg_ms"] for rr in hr["steps"]), max(rr["pcg_ms"] for rr in hr["steps"])],
+        "ptap_ms_range": [min(rr["ptap_ms"] for rr in hr["steps"]), max(rr["ptap_ms"] for rr in hr["steps"])],
+        # the whole solve against the HBM roofline, on the iteration byte model of the
+        # method (every operator block read once per SpMV, as the paper accounts)
+        "pcg_roofline": _pcg_roofline(RL, hr),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / RL.HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": ("bsr_spmv_sym fine 3x3 f64, symmetric reads "

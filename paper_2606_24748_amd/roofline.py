@@ -62,3 +62,22 @@ def ptap_flops(pairs_ap: int, pairs_rap: int, bs: int, nc: int) -> int:
 def coo_bytes(n_coo: int, nnzb: int, br: int, bc: int, val_size: int) -> int:
     """Blocked COO assembly: read every stream block and its map entry once, write A once."""
     return n_coo * (br * bc * val_size + IDX) + nnzb * br * bc * val_size + IDX * (nnzb + 1)
+
+
+def pcg_iteration_bytes(levels, hier_val: int, p_val: int) -> int:
+    """One PCG iteration with a Chebyshev(2) V-cycle: the fine FP64 SpMV of CG (A p),
+    per smoothed level four operator SpMVs, the prolongation and the restriction and
+    about 14 vector passes in the hierarchy's type, plus about 10 fine FP64 vector
+    passes of the CG recurrence (the coarsest dense solve is not counted).  levels:
+    dicts with nbr, bs, nnzb and p_nnzb (blocks of the prolongator to the next level,
+    0 on the coarsest)."""
+    f = levels[0]
+    n0 = f["nbr"] * f["bs"]
+    b = spmv_bytes(f["nbr"], f["nbr"], f["bs"], f["bs"], f["nnzb"], 8, 8) + 10 * 8 * n0
+    for l in range(len(levels) - 1):
+        d, c = levels[l], levels[l + 1]
+        n = d["nbr"] * d["bs"]
+        b += 4 * spmv_bytes(d["nbr"], d["nbr"], d["bs"], d["bs"], d["nnzb"], hier_val, hier_val)
+        b += 2 * spmv_bytes(d["nbr"], c["nbr"], d["bs"], c["bs"], d["p_nnzb"], p_val, hier_val)
+        b += 14 * hier_val * n
+    return b
