@@ -125,6 +125,7 @@ struct amg_s {
     graph = nullptr;
   }
   ~amg_s() {
+    if (A0 && !lv.empty() && A0->f32_copy == lv[0]->A) A0->f32_copy = nullptr;
     drop_graph();
     if (gs) (void)hipStreamDestroy(gs);
     for (auto& e : ev)
@@ -975,10 +976,14 @@ void setup_level_scalars(amg_s* M, int l, std::vector<double>& omega_seg, hipStr
 
 void galerkin_recompute(amg_s* M, hipStream_t s) {
   if (M->T != BLKAMG_F64) {
+    // the FP32 level-0 operator: already written by the COO assembly of the current
+    // values, or cast from them here
     bsr_s* A0f = M->lv[0]->A;
-    cast_values(M->A0->val, BLKAMG_F64, A0f->val, BLKAMG_F32, static_cast<size_t>(M->A0->nnzb) * M->A0->block_elems(),
-                s);
-    A0f->stamp++;
+    if (!(M->A0->f32_copy == A0f && M->A0->f32_copy_stamp == M->A0->stamp)) {
+      cast_values(M->A0->val, BLKAMG_F64, A0f->val, BLKAMG_F32,
+                  static_cast<size_t>(M->A0->nnzb) * M->A0->block_elems(), s);
+      A0f->stamp++;
+    }
   }
   for (size_t l = 0; l + 1 < M->lv.size(); ++l) {
     Level& L = *M->lv[l];
@@ -1348,6 +1353,10 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
       }
     }
     M->T = BLKAMG_F32;
+    // the assembly of A0 writes this level-0 copy beside the values from now on (the
+    // latest such hierarchy on A0; the others cast at their recompute)
+    A0->f32_copy = M->lv[0]->A;
+    A0->f32_copy_stamp = A0->stamp;
   }
   finish_setup(M.get(), s);
   return M.release();

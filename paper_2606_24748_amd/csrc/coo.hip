@@ -33,7 +33,7 @@ template <class T, int BE, int C = 1, int kU = 4>
 __global__ __launch_bounds__(256) void coo_sum_kernel(int64_t nnzb, const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ seg,
                                                       const T* __restrict__ vals, T* __restrict__ out,
-                                                      int add) {
+                                                      int add, float* __restrict__ out32) {
   constexpr int NT = BE / C;  // threads per destination block
   const int64_t total = nnzb * NT;
   const int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -63,12 +63,16 @@ __global__ __launch_bounds__(256) void coo_sum_kernel(int64_t nnzb, const int32_
   T* o = out + t * BE + e;
   if (add) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) o[c] += acc[c];
-  } else {
-    // the matrix is far larger than the caches and is read next by other kernels:
-    // non-temporal stores keep L2 for the gathered values (6 % faster at 128^3)
+    for (int c = 0; c < C; ++c) acc[c] += o[c];
+  }
+  // the matrix is far larger than the caches and is read next by other kernels:
+  // non-temporal stores keep L2 for the gathered values (6 % faster at 128^3)
 #pragma unroll
-    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(acc[c], o + c);
+  for (int c = 0; c < C; ++c) __builtin_nontemporal_store(acc[c], o + c);
+  if (out32) {  // the FP32 copy a mixed-precision hierarchy keeps, rounded from the sums
+    float* o32 = out32 + t * BE + e;
+#pragma unroll
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(static_cast<float>(acc[c]), o32 + c);
   }
 }
 
@@ -87,29 +91,36 @@ __global__ void coo_sum_generic_kernel(int64_t nnzb, int be, const int32_t* __re
   }
 }
 
+// Sums the stream into out; with out32 (3x3 blocks only) also writes the sums rounded
+// to FP32 there.  Returns whether out32 was written.
 template <class T>
-void launch_sum(const coo_plan_s* p, const T* vals, T* out, int add, hipStream_t s) {
-  if (p->nnzb == 0) return;
+bool launch_sum(const coo_plan_s* p, const T* vals, T* out, int add, hipStream_t s, float* out32 = nullptr) {
+  if (p->nnzb == 0) return out32 != nullptr;
   const int be = p->br * p->bc;
   const int64_t total = p->nnzb * be;
   const int64_t grid = (total + 255) / 256;
+  bool copied = false;
   if (be == 1 && grid < INT32_MAX) {
-    coo_sum_kernel<T, 1><<<static_cast<int>(grid), 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
+    coo_sum_kernel<T, 1><<<static_cast<int>(grid), 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add,
+                                                                  nullptr);
   } else if ((be == 9 || be == 18 || be == 36) && grid < INT32_MAX) {
     // three components per thread: a third of the threads, each with three
     // independent sums in flight
     const int g3 = static_cast<int>((total / 3 + 255) / 256);
-    if (be == 9)
-      coo_sum_kernel<T, 9, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
-    else if (be == 18)
-      coo_sum_kernel<T, 18, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
-    else
-      coo_sum_kernel<T, 36, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add);
+    if (be == 9) {
+      coo_sum_kernel<T, 9, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add, out32);
+      copied = out32 != nullptr;
+    } else if (be == 18) {
+      coo_sum_kernel<T, 18, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add, nullptr);
+    } else {
+      coo_sum_kernel<T, 36, 3, 2><<<g3, 256, 0, s>>>(p->nnzb, p->perm.p, p->seg.p, vals, out, add, nullptr);
+    }
   } else {
     const int g2 = static_cast<int>(std::min<int64_t>(grid, 1 << 20));
     coo_sum_generic_kernel<T><<<g2, 256, 0, s>>>(p->nnzb, be, p->perm.p, p->seg.p, vals, out, add);
   }
   HIP_CHECK(hipGetLastError());
+  return copied;
 }
 
 // ---------------------------------------------------------------------------
@@ -418,11 +429,21 @@ int coo_assemble_blocked(coo_plan_t plan, const void* d_vals, int val_dtype, int
               BLKAMG_EINVAL, "matrix shape differs from the plan");
   BLK_REQUIRE(plan->n_valid == 0 || d_vals != nullptr, BLKAMG_EINVAL, "values are NULL");
   hipStream_t s = as_stream(stream);
+  // an FP32 copy kept by a mixed-precision hierarchy is written in the same pass
+  bsr_s* cp = A->f32_copy;
+  const bool want32 = cp != nullptr && val_dtype == BLKAMG_F64 && cp->dtype == BLKAMG_F32 && cp->nnzb == A->nnzb &&
+                      cp->br == A->br && cp->bc == A->bc;
+  bool copied = false;
   if (val_dtype == BLKAMG_F64)
-    launch_sum<double>(plan, static_cast<const double*>(d_vals), static_cast<double*>(A->val), mode == BLKAMG_ADD, s);
+    copied = launch_sum<double>(plan, static_cast<const double*>(d_vals), static_cast<double*>(A->val),
+                                mode == BLKAMG_ADD, s, want32 ? static_cast<float*>(cp->val) : nullptr);
   else
     launch_sum<float>(plan, static_cast<const float*>(d_vals), static_cast<float*>(A->val), mode == BLKAMG_ADD, s);
   A->stamp++;
+  if (copied) {
+    A->f32_copy_stamp = A->stamp;
+    cp->stamp++;
+  }
   BLK_API_END
 }
 

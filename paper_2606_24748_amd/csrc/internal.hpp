@@ -36,6 +36,11 @@ struct bsr_s {
   blk::DevBuf<int32_t> sym_mir;
   int sym_state = 0;
   int sym_dist = 0;  // median over rows of the distance to the row's first lower column
+  // FP32 copy of the values that a mixed-precision hierarchy keeps as its level-0
+  // operator (same pattern): coo_assemble_blocked writes it beside the values, and
+  // f32_copy_stamp is the stamp it then matches (the hierarchy casts otherwise)
+  bsr_s* f32_copy = nullptr;
+  uint64_t f32_copy_stamp = 0;
   // host copy of the pattern (filled on demand or at creation)
   std::vector<int32_t> h_rowptr, h_colidx;
   bool h_pattern = false;

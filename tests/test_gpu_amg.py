@@ -203,3 +203,40 @@ def test_vcycle_on_fp32_vectors(nrhs):
     with pytest.raises(B.BlkAmgError) as e:
         B.vcycle_apply(M64, r.float().contiguous(), z32, nrhs=nrhs)
     assert e.value.code == B.EINVAL
+
+
+def test_f32_level0_copy_written_by_the_assembly():
+    """A mixed-precision hierarchy's FP32 level-0 operator: after COO assembly of new
+    values it is written in the same pass (the recompute then skips its cast); once a
+    second hierarchy on the same operator holds the assembly's copy, the first one's
+    recompute casts.  Either way it is the FP64 operator rounded to FP32, bit for bit,
+    and destroying the second hierarchy changes nothing for the first."""
+    m, i, j, v, A = q1_problem(8, mat_seed=4)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    o = B.blkamg_opts_default()
+    o.hier_dtype, o.p_dtype = B.F32, B.F32
+
+    def level0_matches(M):
+        A0f = M.level(0)[0].arrays()[2]
+        return torch.equal(A0f, HA.arrays()[2].float())
+
+    M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+    assert level0_matches(M)
+    for scale in (1.5, 0.25):
+        B.coo_assemble_blocked(plan, dev(v * scale), B.INSERT, HA)
+        assert level0_matches(M)  # written by the assembly itself
+        B.amg_galerkin_recompute(M)
+        assert level0_matches(M)
+    M2 = B.amg_setup(HA, m.coords, m.dirichlet, o)  # now the registered copy
+    B.coo_assemble_blocked(plan, dev(v * 3.0), B.ADD, HA)  # values 0.25 v + 3 v
+    B.amg_galerkin_recompute(M)  # M's copy is no longer written by the assembly: cast
+    assert level0_matches(M) and level0_matches(M2)
+    del M2
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    B.amg_galerkin_recompute(M)
+    assert level0_matches(M)
+    b = dev(synth.rhs(m, 1))
+    x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+    code, its, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+    assert code == B.OK and rel <= 1e-8
