@@ -807,6 +807,9 @@ def _ptap_roofline(RL, r, fp64=False):
            "traffic": measured_traffic(PTAP_TRAFFIC_RECORD, PTAP_TRAFFIC_SOURCES) if fp64 else None,
            "kernel": "ptap_numeric, all levels", "bytes_per_recompute": r["ptap_alg_bytes"],
            "median_ms": ms}
+    if out["traffic"]:
+        out["traffic_GBs"] = out["traffic"] / (ms * 1e-3) / 1e9
+        out["traffic_frac"] = out["traffic_GBs"] / RL.HBM_PEAK_GBS
     if r.get("ptap_flops"):
         tf = r["ptap_flops"] / (ms * 1e-3) / 1e12
         pk = RL.FP64_PEAK_TFLOPS if fp64 else RL.FP32_PEAK_TFLOPS
@@ -971,6 +974,10 @@ def main(argv=None):
         "cold_setup_s": {"device": cold_setup["device_s"], "host_symbolic": cold_setup["host_symbolic_s"]},
         "cpu_baseline": cpu,
     }
+    rl = out["roofline"]
+    if rl["traffic"]:  # the counters' bytes over the same duration: what the kernel really moved
+        rl["traffic_GBs"] = rl["traffic"] / (spmv_ms * 1e-3) / 1e9
+        rl["traffic_frac"] = rl["traffic_GBs"] / RL.HBM_PEAK_GBS
     alt = {}
     for var, r in results.items():
         if var == head:
