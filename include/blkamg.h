@@ -357,6 +357,14 @@ typedef struct {
                                (A itself when A is symmetric, as CG requires; the results
                                then differ from full reads only in the grouping of the row
                                sums).  0: read every block */
+  int32_t ap_residual;      /* 1 (default): with one right-hand side, the post-smoothing's
+                               first residual on a level whose Galerkin product A P costs
+                               fewer bytes to read than A (the FP32 fine level) is updated
+                               from the restricted residual, r - (A P) e_c, with the A P
+                               that the last recompute formed (paper §2.1: the same residual
+                               as f - A (x + P e_c) up to rounding).  Used only while A and
+                               P still hold the values that A P was formed from; otherwise,
+                               and with 0, the residual is f - A x */
 } blkamg_opts;
 
 /* Fill *o with the defaults listed above. */

@@ -65,6 +65,7 @@ class Opts(C.Structure):
         ("eig_model", C.c_void_p),
         ("mlp_guard", C.c_int32),
         ("sym_spmv", C.c_int32),
+        ("ap_residual", C.c_int32),
     ]
 
 

@@ -17,6 +17,7 @@
 
 #include "amg_kernels.hpp"
 #include "mlp.hpp"
+#include "ptap_plan.hpp"
 #include "sa_host.hpp"
 
 namespace blk {
@@ -42,6 +43,11 @@ struct Level {
   DevBuf<int32_t> d_act_off;           // block-row offsets of the smoothed segments
   DevBuf<uint16_t> d_row_seg;          // segment of each smoothed row (several segments only)
   SegGrid lgrid;                       // Lanczos dots over the smoothed dofs
+  // A P of this level (rows of A_act x rows of the next level), kept by the Galerkin plan
+  // of the next level's operator: a view over the plan's arrays (refilled at each use),
+  // and the stamps of A and P when the Galerkin pass last formed it (0 = never)
+  std::unique_ptr<bsr_s> AP;
+  uint64_t ap_stamp = 0, ap_pstamp = 0;
   const int32_t* mir = nullptr;        // symmetric-read mirror index of A (nullptr = full reads)
   int sym_dist = 0;                    // A's typical lower bandwidth (workgroup runs of the symmetric reads)
   DevBuf<char> dinv;                   // [act_rows][bs][bs] hierarchy dtype
@@ -463,6 +469,44 @@ void coarse_apply(Level& L, const TV* f, TV* out, hipStream_t s) {
   HIP_CHECK(hipGetLastError());
 }
 
+// The Galerkin pass has just formed the level's A P from its current A and P.
+void note_ap(Level& L) {
+  L.ap_stamp = L.A->stamp;
+  L.ap_pstamp = L.P ? L.P->stamp : 0;
+}
+
+// The level's A P when the post-smoothing may update its residual with it: the option
+// is on, reading A P costs fewer bytes than reading A (block bytes plus an index each;
+// never against the symmetric reads, which read less than either), and A and P still
+// hold the values A P was formed from.  nullptr otherwise.  The view is refilled from
+// the next level's plan on every call, so it never outlives the arrays it points to.
+const bsr_s* ap_for(amg_s* M, int l) {
+  Level& L = *M->lv[l];
+  if (!M->o.ap_residual || L.bs != 3 || L.mir || !L.P || L.P->bc != 6 || L.n_act == 0 ||
+      static_cast<size_t>(l) + 1 >= M->lv.size() || L.A->dtype != M->T)
+    return nullptr;
+  if (L.ap_stamp != L.A->stamp || L.ap_pstamp != L.P->stamp) return nullptr;
+  const auto* pl = static_cast<const PtapPlan*>(M->lv[l + 1]->A->ext.get());
+  if (!pl || pl->A != L.A_act.get() || pl->P != L.P.get() || pl->n_ap_rows != L.act_rows || pl->ap_nslots <= 0)
+    return nullptr;
+  const double vs = static_cast<double>(dtype_size(M->T));
+  const double ap_bytes = static_cast<double>(pl->ap_nslots) * (L.bs * L.P->bc * vs + 4.0);
+  const double a_bytes = static_cast<double>(L.A_act->nnzb) * (L.bs * L.bs * vs + 4.0);
+  if (!(ap_bytes < a_bytes)) return nullptr;
+  if (!L.AP) L.AP = std::make_unique<bsr_s>();
+  bsr_s* V = L.AP.get();
+  V->nbr = pl->n_ap_rows;
+  V->nbc = L.P->nbc;
+  V->br = L.bs;
+  V->bc = L.P->bc;
+  V->dtype = M->T;  // A P is formed in the accumulation type, the hierarchy's own
+  V->nnzb = pl->ap_nslots;
+  V->rowptr = pl->ap_rowptr.p;
+  V->colidx = pl->ap_colidx.p;
+  V->val = pl->ap_val.p;
+  return V;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle
 // ---------------------------------------------------------------------------
@@ -514,8 +558,16 @@ void vcycle_level(amg_s* M, int l, const TV* f, TV* out, hipStream_t s) {
   spmv(R, 1.0, r, 0.0, fc, M->T, NR, s);
   vcycle_level<TV, NR>(M, l + 1, fc, oc, s);
   spmv(L.P.get(), 1.0, oc, 1.0, x, M->T, NR, s);
-  // post-smoothing from x
-  {
+  // post-smoothing from x; its first residual f - A x, or, with the Galerkin pass's
+  // A P, r - (A P) e_c from the restricted residual still in r (each row's r is read
+  // and rewritten by the same lanes; the product gathers only e_c)
+  const bsr_s* APv = nullptr;
+  if constexpr (NR == 1) APv = ap_for(M, l);
+  if (APv) {
+    EpiSmooth<M_INITX, TV, TV> e{r, r, nullptr, d, x, out, dinv, sc, rseg, 0};
+    launch_rows<3, 6, 1, TV, TV, TV>(lanes_for(APv, 1), APv->nbr, APv->rowptr, APv->colidx,
+                                     static_cast<const TV*>(APv->val), oc, e, s);
+  } else {
     EpiSmooth<M_INITX, TV, TV> e{f, r, nullptr, d, x, out, dinv, sc, rseg, 0};
     smooth<M_INITX, NR, TV>(A, L.mir, L.sym_dist, x, e, s);
   }
@@ -990,6 +1042,7 @@ void galerkin_recompute(amg_s* M, hipStream_t s) {
     if (L.n_act == 0) continue;
     const int rc = ptap_numeric(L.A_act.get(), L.P.get(), M->lv[l + 1]->A, s);
     if (rc != BLKAMG_OK) fail(rc, std::string("ptap_numeric: ") + blkamg_last_error());
+    note_ap(L);
   }
 }
 
@@ -1088,6 +1141,7 @@ void check_opts(const blkamg_opts& o) {
   BLK_REQUIRE(o.agg_mode == BLKAMG_AGG_GREEDY || o.agg_mode == BLKAMG_AGG_LUBY, BLKAMG_EINVAL, "bad agg_mode");
   BLK_REQUIRE(o.growth_steps >= 1 && o.growth_steps <= 16, BLKAMG_EINVAL, "growth_steps must be in 1..16");
   BLK_REQUIRE(o.sym_spmv == 0 || o.sym_spmv == 1, BLKAMG_EINVAL, "sym_spmv must be 0 or 1");
+  BLK_REQUIRE(o.ap_residual == 0 || o.ap_residual == 1, BLKAMG_EINVAL, "ap_residual must be 0 or 1");
   BLK_REQUIRE(o.mlp_guard == BLKAMG_GUARD_SMOOTHER || o.mlp_guard == BLKAMG_GUARD_PCG, BLKAMG_EINVAL,
               "mlp_guard must be BLKAMG_GUARD_SMOOTHER or BLKAMG_GUARD_PCG");
 }
@@ -1320,6 +1374,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
     next->A = Cm;
     rc = ptap_numeric(A, L.P.get(), Cm, stream);
     if (rc != BLKAMG_OK) fail(rc, std::string("ptap_numeric: ") + blkamg_last_error());
+    note_ap(L);
     dB = std::move(dBc);
     dir.clear();
     M->lv.push_back(std::move(next));
@@ -1350,6 +1405,7 @@ amg_s* setup_impl(bsr_t A0, int32_t n_inst, const int32_t* h_row0, const double*
         if (rc != BLKAMG_OK) fail(rc, std::string("ptap_numeric: ") + blkamg_last_error());
         HIP_CHECK(hipStreamSynchronize(s));
         L.P = std::move(Pf);
+        note_ap(L);
       }
     }
     M->T = BLKAMG_F32;
@@ -1659,6 +1715,7 @@ void blkamg_opts_default(blkamg_opts* o) {
   o->eig_model = nullptr;
   o->mlp_guard = BLKAMG_GUARD_SMOOTHER;
   o->sym_spmv = 1;
+  o->ap_residual = 1;
 }
 
 int amg_setup(bsr_t A0, const double* h_coords, const uint8_t* h_dirichlet, const blkamg_opts* opts, void* stream,

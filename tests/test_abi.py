@@ -78,6 +78,7 @@ def test_default_options():
     assert (o.max_levels, o.coarse_eq_limit, o.cheb_degree, o.lanczos_steps) == (10, 1000, 2, 10)
     assert (o.cheb_lo, o.cheb_hi, o.strength_eps) == (0.1, 1.1, 0.0)
     assert o.lanczos_seed == 0x5EED and abs(o.omega_scale - 4 / 3) < 1e-15
+    assert o.sym_spmv == 1 and o.ap_residual == 1
 
 
 def test_single_hip_runtime_after_import():

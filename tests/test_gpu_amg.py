@@ -181,6 +181,54 @@ def test_symmetric_reads_give_identical_vcycle_and_pcg(hier):
     assert rel2(out[1][2].numpy(), out[0][2].numpy()) <= 1e-9 and out[0][3] == out[1][3]
 
 
+@pytest.mark.parametrize("hier", [B.F64, B.F32])
+def test_ap_residual_update(hier):
+    """ap_residual = 1 (the default): the post-smoothing's first fine residual is updated
+    as r - (A P) e_c from the Galerkin pass's A P instead of recomputed as f - A x (0), on
+    levels where A P is cheaper to read (every block read: sym_spmv = 0 here, so FP64 takes
+    it too).  The same residual up to rounding: the V-cycles differ (A P was used) by
+    roundoff only, CG takes the same iterations.  With new values assembled but not yet
+    recomputed, A P no longer belongs to A and the V-cycle is that of ap_residual = 0 bit
+    for bit; after the recompute A P is used again."""
+    print(f"ap residual hier={hier}", flush=True)
+    m, i, j, v, A = q1_problem(14, mat_seed=5)
+    plan, HA = B.coo_plan_create(m.n_nodes, m.n_nodes, 3, 3, i, j)
+    B.coo_assemble_blocked(plan, dev(v), B.INSERT, HA)
+    r = dev(np.random.default_rng(9).uniform(-1, 1, m.n_dof))
+    b = dev(synth.rhs(m, 4))
+    Ms = []
+    for ap in (0, 1):
+        o = B.blkamg_opts_default()
+        o.hier_dtype, o.p_dtype, o.sym_spmv, o.ap_residual = hier, hier, 0, ap
+        M = B.amg_setup(HA, m.coords, m.dirichlet, o)
+        B.amg_smoother_refresh(M)
+        Ms.append(M)
+
+    def vc(M):
+        z = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+        B.vcycle_apply(M, r, z)
+        return z.cpu().numpy()
+
+    tol = 1e-12 if hier == B.F64 else 1e-5
+    z0, z1 = vc(Ms[0]), vc(Ms[1])
+    assert 0.0 < rel2(z1, z0) <= tol
+    its = []
+    for M in Ms:
+        x = torch.zeros(m.n_dof, dtype=torch.float64, device="cuda")
+        code, it, rel = B.pcg_solve(HA, M, b, x, rtol=1e-8)
+        assert code == B.OK and rel <= 1e-8
+        its.append(it)
+    assert its[0] == its[1]
+    if hier == B.F64:  # both hierarchies read the caller's operator itself
+        B.coo_assemble_blocked(plan, dev(1.5 * v), B.INSERT, HA)
+        assert np.array_equal(vc(Ms[0]), vc(Ms[1]))
+        for M in Ms:
+            B.amg_galerkin_recompute(M)
+            B.amg_smoother_refresh(M)
+        z0, z1 = vc(Ms[0]), vc(Ms[1])
+        assert 0.0 < rel2(z1, z0) <= tol
+
+
 @pytest.mark.parametrize("nrhs", [1, 8])
 def test_vcycle_on_fp32_vectors(nrhs):
     """vcycle_apply_ex with FP32 vectors on an F32 hierarchy runs the same FP32 V-cycle
